@@ -1,0 +1,208 @@
+/*
+ * scint.h -- C ABI of the MI355X (gfx950) phase-screen + Fresnel propagation
+ * library (libscint.so).
+ *
+ * The operations follow Habibi, Moniez, Ansari & Rahvar, "Simulation of
+ * optical interstellar scintillation" (A&A 2013, arXiv:1301.0514).  Citations
+ * name the section and equation of that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids are square, N x N pixels of side `delta` (Sect. 3.1).  Supported N
+ *    are listed by ps_supported_size(); every other N returns PS_E_SIZE.
+ *  - Arrays are device memory owned by the caller, contiguous, row-major
+ *    [batch][N][N] with y (row) slow and x fast.  Real arrays hold float
+ *    (dtype PS_F32) or double (PS_F64).  The library never frees caller memory.
+ *  - delta, lambda, z, r_diff and source radii share one length unit of the
+ *    caller's choice.  The Fresnel radius is R_F = sqrt(lambda z / 2 pi)
+ *    (Sect. 2, Eq. Rfresnel); the screen-observer distance z is the effective
+ *    distance of the footnote to Eq. Rfresnel when the source is not far.
+ *  - Work is enqueued asynchronously on `hip_stream` (a hipStream_t; NULL is
+ *    the null stream); the caller synchronises.  Entry points returning host
+ *    scalars (m_out, loss_out, phi_dot_grad_out) synchronise the stream first.
+ *  - The library keeps a per-device cache of FFT twiddle tables, disk spectra
+ *    and a per-stream workspace; the first call of a given shape allocates it
+ *    (hipMalloc), later calls of that shape or smaller allocate nothing.  Calls
+ *    that overlap on the same stream are ordered by the stream; calls on two
+ *    streams use two workspaces.  ps_release_cache() frees everything.
+ *  - Every entry point returns a ps_status.  Arguments are validated before
+ *    anything is launched; on error nothing is written and ps_last_error()
+ *    returns a message (thread-local).  PS_E_DEVICE reports a failing HIP call.
+ *  - All arithmetic of the FP32 path is in FP32, with FFT twiddles and chirp
+ *    tables computed in FP64 and rounded once, and the phase arguments of
+ *    exp(i s phi) reduced modulo 2 pi in FP64 before the FP32 sine/cosine.
+ */
+#ifndef SCINT_H
+#define SCINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { PS_F32 = 0, PS_F64 = 1 } ps_dtype;
+
+typedef enum {
+    PS_OK = 0,
+    PS_E_NULL = -1,          /* a required pointer is NULL                      */
+    PS_E_SIZE = -2,          /* N (or a count) unsupported / too large          */
+    PS_E_PARAM = -3,         /* a physical parameter is non-finite or out of range */
+    PS_E_DTYPE = -4,         /* dtype is not PS_F32 or PS_F64                   */
+    PS_E_ALLOC = -5,         /* device memory for the workspace or cache failed */
+    PS_E_DEVICE = -6,        /* a HIP call or kernel launch failed              */
+    PS_E_ALIAS = -7,         /* output overlaps an input where that is not allowed */
+    PS_E_UNIMPLEMENTED = -8  /* combination not provided by this build          */
+} ps_status;
+
+/* 1 if N is supported for dtype, else 0.  The FP32 set is
+ * {16,32,...,16384} (powers of two) and {40,80,100,160,200,320,400,640,1000,
+ * 1280,2000,2560,4000,5000,8000,10000} (2^a 5^b); the FP64 set is the same
+ * up to 8192.  */
+int ps_supported_size(int N, int dtype);
+
+/* Number of supported sizes for dtype, and the i-th of them (ascending). */
+int ps_num_supported_sizes(int dtype);
+int ps_supported_size_at(int dtype, int i);
+
+/*
+ * ps_generate -- random phase screens (Sect. 3.1, Eqs. spectre and densite).
+ *
+ * For realisation r = first_realisation + b (b = 0..n_real-1) and every Fourier
+ * pixel k = (kx, ky) of the FFT grid (kx, ky in [0, N), signed frequency
+ * k' = k for k < N/2 else k - N):
+ *   counter = (kx, ky, r, 0), key = (seed mod 2^32, seed >> 32);
+ *   (w0..w3) = Philox4x32-10(counter, key);
+ *   u1 = ((((w0 << 32) | w1) >> 11) + 1/2) 2^-53, u2 likewise from (w2, w3);
+ *   g = sqrt(-2 ln u1) (cos 2 pi u2 + i sin 2 pi u2);
+ *   c[k] = sqrt(S(q)) / N * g / sqrt(2),  q = |k'| / N cycles per pixel,
+ *   with S(q) = R^2 / (2 (2 pi)^(beta-1) f(beta)) (R q)^(-beta),
+ *   f(beta) = 2^-beta beta Gamma(-beta/2) / Gamma(beta/2), R = r_diff/delta;
+ *   c[0] = 0.
+ * The screen is phi[m] = sqrt(2) Re sum_k c[k] exp(+2 pi i k.m / N) (radians).
+ * The "Gaussian of width L_x L_y S" of the paper is read as variance L_x L_y S
+ * per part, so that <|F_phi|^2> = L_x L_y S (Eq. densite) with c = F_phi/L^2.
+ *
+ *   N, delta          grid size and pixel side (delta > 0)
+ *   r_diff            diffraction radius R_diff (> 0), where D_phi = 1 (Eq. dphi)
+ *   beta              spectral exponent, 2 < beta < 4 (11/3 = Kolmogorov)
+ *   seed, first_realisation, n_real   noise stream selection (n_real >= 1)
+ *   phi_out           device [n_real][N][N] real (dtype)
+ * A warning (ps_last_warning) is set when delta >= r_diff/2, the sampling
+ * criterion of Sect. 3.2.2.
+ */
+int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed,
+                uint32_t first_realisation, int n_real, int dtype, void *phi_out,
+                void *hip_stream);
+
+/*
+ * fresnel_propagate -- point-source illumination pattern (Sect. 2, Eq. hxy).
+ *
+ * For each of the n screens phi (radians, scaled by phase_scale s):
+ *   U = exp(i s phi);  A = N^-2 IDFT[ H(k) DFT[U](k) ];  I = |A|^2,
+ *   H(k) = H1(kx') H1(ky'),  H1(k') = exp(-i 2 pi^2 rho^2 k'^2 / N^2),
+ *   rho = R_F / delta = sqrt(lambda z / 2 pi) / delta,
+ * which is the Fresnel-Huygens integral of Eq. hxy on the periodic screen,
+ * normalised so that a uniform screen gives I = 1 (so <I> = 1).  At
+ * N = 2 pi rho^2 it equals the direct sum of Eq. hxy and the one-FFT form of
+ * Sect. 3.2 (Eqs. intens, Gxy).  phase_scale = lambda_ref / lambda re-uses a
+ * screen given at lambda_ref (phi scales as 1/lambda, Sect. 2, Eq. phiNl).
+ *
+ *   phi       device [n][N][N] real (input, not modified)
+ *   I_out     device [n][N][N] real; must not overlap phi (PS_E_ALIAS)
+ */
+int fresnel_propagate(int N, double delta, double lambda, double z, const void *phi,
+                      double phase_scale, int n, int dtype, void *I_out, void *hip_stream);
+
+/*
+ * ps_screen_fresnel -- ps_generate followed by fresnel_propagate with s = 1,
+ * fused so that the screen need not go through device memory.
+ *   phi_out   optional device [n_real][N][N] real copy of the screen, or NULL
+ *   I_out     device [n_real][N][N] real
+ */
+int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t seed,
+                      uint32_t first_realisation, int n_real, double lambda, double z,
+                      int dtype, void *phi_out, void *I_out, void *hip_stream);
+
+/*
+ * illumination_polychromatic -- co-added pattern over a passband
+ * (Sect. 3.2.4).  The same screen phi_ref, given at lambda_ref, is seen at each
+ * lambda_j with phase scale s_j = lambda_ref / lambda_j (Eq. phiNl) and
+ * Fresnel radius sqrt(lambda_j z / 2 pi) (Eq. Rfresnel):
+ *   I = sum_j w_j I_j / sum_j w_j.
+ *   lambdas, weights   host arrays of n_lambda entries; weights may be NULL
+ *                      (equal weights); weights >= 0 with a positive sum
+ *   n_lambda           1 .. 4096
+ *   phi_ref   device [n_real][N][N] real;  I_out device [n_real][N][N] real
+ */
+int illumination_polychromatic(int N, double delta, double z, const void *phi_ref,
+                               double lambda_ref, const double *lambdas,
+                               const double *weights, int n_lambda, int n_real, int dtype,
+                               void *I_out, void *hip_stream);
+
+/*
+ * source_smear -- extended source (Sect. 3.2.3, Eq. iprh): circular
+ * convolution of each pattern with a uniform disk of projected radius R_s,
+ *   I_ext[m] = sum_d P[d] I[m - d],  P[d] = 1/n_R if |d| <= R_s/delta else 0,
+ * |d| the minimum-image distance between pixel centres on the periodic grid,
+ * n_R the number of such pixels (so R_s < delta gives the identity and the
+ * mean is preserved).  Computed by FFT multiplication.
+ *   I_in      device [n_real][N][N] real
+ *   radii     host array of n_r radii R_s >= 0 (length unit of delta), n_r <= 64
+ *   I_out     device [n_real][n_r][N][N] real; may equal I_in only if n_r == 1
+ */
+int source_smear(int N, double delta, const void *I_in, const double *radii, int n_r,
+                 int n_real, int dtype, void *I_out, void *hip_stream);
+
+/*
+ * fresnel_propagate_vjp -- adjoint of fresnel_propagate (vector-Jacobian
+ * product) for a loss L(I) whose gradient dL/dI is grad_I:
+ *   g_A = 2 grad_I A;  g_U = N^-2 IDFT[ conj(H) DFT[g_A] ];
+ *   dL/dphi = s Im(g_U conj(U)).
+ * The forward field A is recomputed from phi (nothing is kept between calls).
+ *   phi, grad_I        device [n][N][N] real
+ *   grad_phi_out       device [n][N][N] real; must not overlap phi or grad_I
+ *   phi_dot_grad_out   optional host array of n doubles: sum_m phi dL/dphi
+ *                      per screen (FP64), from which
+ *                      dL/dlog R_diff = ((2 - beta)/2) phi_dot_grad, since the
+ *                      screen scales as R_diff^((2-beta)/2) for fixed noise.
+ */
+int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const void *phi,
+                          double phase_scale, const void *grad_I, int n, int dtype,
+                          void *grad_phi_out, double *phi_dot_grad_out, void *hip_stream);
+
+/*
+ * ps_modulation_index -- m = sigma_I / mean(I) per pattern (Sect. 4),
+ * population sigma over all N^2 pixels, FP64 accumulation in a fixed order
+ * (bitwise reproducible).
+ *   I       device [n][N][N] real
+ *   m_out   host array of n doubles;  mean_out optional host array of n doubles
+ */
+int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out,
+                        double *mean_out, void *hip_stream);
+
+/*
+ * ps_l2_loss -- L = sum_m (I - I_target)^2 per pattern and its gradient
+ * dL/dI = 2 (I - I_target).
+ *   grad_out   optional device [n][N][N] real
+ *   loss_out   optional host array of n doubles (FP64 accumulation)
+ */
+int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
+               void *grad_out, double *loss_out, void *hip_stream);
+
+/* Message for the last non-OK status of this thread ("" if none). */
+const char *ps_last_error(void);
+/* Message for the last warning of this thread ("" if none); cleared by every call. */
+const char *ps_last_warning(void);
+/* Free every cached table and workspace on every device.  Not to be called
+ * while work that uses them is in flight. */
+int ps_release_cache(void);
+/* Library version (major * 10000 + minor * 100 + patch). */
+int ps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCINT_H */

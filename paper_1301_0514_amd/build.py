@@ -1,0 +1,93 @@
+"""Build libscint.so (the gfx950 HIP library) in-tree with hipcc.
+
+Usage: python -m paper_1301_0514_amd.build [--jobs N] [--verbose]
+
+Compiles the row-pass kernel once per (precision, program), the auxiliary
+kernels and the host C ABI, and links them into
+paper_1301_0514_amd/lib/libscint.so.  Every call rebuilds from scratch.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIBDIR = os.path.join(PKG, "lib")
+LIB = os.path.join(LIBDIR, "libscint.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+PROGRAMS = ["ProgNoise", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgPropIntensity",
+            "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX"]
+
+# gfx950 only; packed FP32 instructions are disabled (the compiler would
+# otherwise form them from float code).
+DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-Wno-unused-command-line-argument"]
+
+
+def _jobs() -> list[tuple[list[str], str]]:
+    jobs = []
+    for real, is64 in (("float", 0), ("double", 1)):
+        for prog in PROGRAMS:
+            obj = os.path.join(BUILD, f"row_{real}_{prog}.o")
+            cmd = [HIPCC, *DEVICE_FLAGS, f"-DSCINT_REAL={real}", f"-DSCINT_PROG={prog}",
+                   f"-DSCINT_IS_F64={is64}", "-c", os.path.join(CSRC, "row_inst.hip"), "-o", obj]
+            jobs.append((cmd, obj))
+    for src in ("aux_kernels.hip", "scint_api.cpp", "twiddles.cpp"):
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        lang = [] if src.endswith(".hip") else ["-x", "hip"]
+        cmd = [HIPCC, *DEVICE_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        jobs.append((cmd, obj))
+    return jobs
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    if jobs is None:
+        jobs = int(os.environ.get("MAX_JOBS", "0")) or min(16, os.cpu_count() or 4)
+    shutil.rmtree(BUILD, ignore_errors=True)
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(LIBDIR, exist_ok=True)
+    t0 = time.time()
+    work = _jobs()
+
+    def run(item):
+        cmd, obj = item
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+        if verbose:
+            print("built", os.path.basename(obj), flush=True)
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(run, work))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s%s" % (r.stdout, r.stderr))
+    os.replace(tmp, LIB)
+    if verbose:
+        print("linked %s in %.1f s" % (LIB, time.time() - t0), flush=True)
+    return LIB
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--verbose", action="store_true")
+    a = ap.parse_args(argv)
+    build(a.jobs, a.verbose)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,38 @@
+// aux_kernels.h -- launchers of the non-FFT kernels: batched transposes,
+// chirp tables, disk images, reductions and the L2 loss.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scint {
+
+// out[b][x][y] = in[b][y][x] for b < nbatch; elem_bytes in {4, 8, 16}.
+hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes,
+                            hipStream_t stream);
+
+// tab[j][k] = scale * exp(-2 pi i a[j] k'^2), k' the signed frequency of k,
+// for j < n (n <= 64); a[j] = pi rho_j^2 / N^2 (turns per k'^2).  The turn
+// count is formed and reduced in FP64 and the sine/cosine taken in FP64.
+hipError_t launch_chirp_tables(void *tab, int N, const double *a, int n, double scale, bool f64,
+                               hipStream_t stream);
+
+// img[y][x] = value if dx^2 + dy^2 <= r2 (minimum-image offsets of pixel
+// (x, y) from the origin), else 0.
+hipError_t launch_disk_image(void *img, int N, double r2, double value, bool f64, hipStream_t stream);
+
+// partials[b * nblk + blk] = sum over block blk's share of batch b of
+// (x - center[b])^power  (center may be NULL = 0; power 1 or 2), FP64.
+hipError_t launch_block_sums(const void *x, int64_t n_per_batch, int nbatch, const double *center,
+                             int power, int nblk, bool f64, double *partials, hipStream_t stream);
+
+// out[b] = scale * sum_blk partials[b * nblk + blk], fixed-order tree.
+hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,
+                                hipStream_t stream);
+
+// grad[i] = 2 (I[i] - It[i]) (if grad != NULL); partials as launch_block_sums
+// of (I - It)^2.
+hipError_t launch_l2_loss(const void *I, const void *It, void *grad, int64_t n_per_batch, int nbatch,
+                          int nblk, bool f64, double *partials, hipStream_t stream);
+
+}  // namespace scint

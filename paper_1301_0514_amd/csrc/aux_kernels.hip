@@ -1,0 +1,207 @@
+// aux_kernels.hip -- batched transposes, chirp tables, disk images and
+// deterministic reductions for gfx950.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aux_kernels.h"
+#include "device_common.hpp"
+
+namespace scint {
+
+// ---------------------------------------------------------------- transpose
+// TILE x TILE tile through LDS (one padding column), 256 threads; each
+// thread moves TILE*TILE/256 elements.  Reads and writes are row-contiguous.
+template <typename T, int TILE>
+__global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ in, T *__restrict__ out, int N) {
+    __shared__ T tile[TILE][TILE + 1];
+    constexpr int ROWS = 256 / TILE;
+    const int tx = threadIdx.x % TILE, ty = threadIdx.x / TILE;
+    const int x0 = blockIdx.x * TILE, y0 = blockIdx.y * TILE;
+    const int64_t base = (int64_t)blockIdx.z * N * N;
+    const T *src = in + base;
+    T *dst = out + base;
+#pragma unroll
+    for (int r = ty; r < TILE; r += ROWS) {
+        const int y = y0 + r, x = x0 + tx;
+        if (y < N && x < N) tile[r][tx] = src[(int64_t)y * N + x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < TILE; r += ROWS) {
+        const int x = x0 + r, y = y0 + tx;
+        if (x < N && y < N) dst[(int64_t)x * N + y] = tile[tx][r];
+    }
+}
+
+struct alignas(16) Elem16 {
+    double a, b;
+};
+
+hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes,
+                            hipStream_t stream) {
+    for (int64_t b0 = 0; b0 < nbatch; b0 += 65535) {
+        const int nb = (int)((nbatch - b0) < 65535 ? (nbatch - b0) : 65535);
+        const int64_t off = b0 * (int64_t)N * N;
+        if (elem_bytes == 4) {
+            constexpr int TILE = 64;
+            dim3 grid((N + TILE - 1) / TILE, (N + TILE - 1) / TILE, nb);
+            hipLaunchKernelGGL((transpose_kernel<float, TILE>), grid, dim3(256), 0, stream,
+                               static_cast<const float *>(in) + off, static_cast<float *>(out) + off, N);
+        } else if (elem_bytes == 8) {
+            constexpr int TILE = 64;
+            dim3 grid((N + TILE - 1) / TILE, (N + TILE - 1) / TILE, nb);
+            hipLaunchKernelGGL((transpose_kernel<double, TILE>), grid, dim3(256), 0, stream,
+                               static_cast<const double *>(in) + off, static_cast<double *>(out) + off, N);
+        } else if (elem_bytes == 16) {
+            constexpr int TILE = 32;
+            dim3 grid((N + TILE - 1) / TILE, (N + TILE - 1) / TILE, nb);
+            hipLaunchKernelGGL((transpose_kernel<Elem16, TILE>), grid, dim3(256), 0, stream,
+                               static_cast<const Elem16 *>(in) + off, static_cast<Elem16 *>(out) + off, N);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------- chirp
+struct ChirpArgs {
+    double a[64];
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void chirp_kernel(cpx<Real> *tab, int N, ChirpArgs args, int n, double scale) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y;
+    if (k >= N || j >= n) return;
+    const double kk = (double)(k < N / 2 ? k : k - N);
+    const double turns = args.a[j] * (kk * kk);
+    const double f = turns - rint(turns);
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    tab[(int64_t)j * N + k] = {(Real)(scale * c), (Real)(-scale * s)};
+}
+
+hipError_t launch_chirp_tables(void *tab, int N, const double *a, int n, double scale, bool f64,
+                               hipStream_t stream) {
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    ChirpArgs args{};
+    for (int j = 0; j < n; ++j) args.a[j] = a[j];
+    dim3 grid((N + 255) / 256, n);
+    if (f64)
+        hipLaunchKernelGGL((chirp_kernel<double>), grid, dim3(256), 0, stream, static_cast<cpx<double> *>(tab), N,
+                           args, n, scale);
+    else
+        hipLaunchKernelGGL((chirp_kernel<float>), grid, dim3(256), 0, stream, static_cast<cpx<float> *>(tab), N,
+                           args, n, scale);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- disk
+template <typename Real>
+__global__ __launch_bounds__(256) void disk_kernel(Real *img, int N, double r2, double value) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= N) return;
+    const double dx = (double)(x < N / 2 ? x : x - N);
+    const double dy = (double)(y < N / 2 ? y : y - N);
+    img[(int64_t)y * N + x] = (dx * dx + dy * dy <= r2) ? (Real)value : (Real)0;
+}
+
+hipError_t launch_disk_image(void *img, int N, double r2, double value, bool f64, hipStream_t stream) {
+    dim3 grid((N + 255) / 256, N);
+    if (f64)
+        hipLaunchKernelGGL((disk_kernel<double>), grid, dim3(256), 0, stream, static_cast<double *>(img), N, r2,
+                           value);
+    else
+        hipLaunchKernelGGL((disk_kernel<float>), grid, dim3(256), 0, stream, static_cast<float *>(img), N, r2,
+                           value);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+// Block tree over 256 FP64 partials in LDS (fixed order).
+__device__ __forceinline__ double block_tree_sum(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void block_sums_kernel(const Real *__restrict__ x, int64_t n, const double *center,
+                                                         int power, double *partials) {
+    __shared__ double red[256];
+    const int b = blockIdx.y, nblk = gridDim.x;
+    const Real *xb = x + (int64_t)b * n;
+    const double c = center ? center[b] : 0.0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
+        const double d = (double)xb[i] - c;
+        acc += (power == 2) ? d * d : d;
+    }
+    const double tot = block_tree_sum(acc, red);
+    if (threadIdx.x == 0) partials[(int64_t)b * nblk + blockIdx.x] = tot;
+}
+
+hipError_t launch_block_sums(const void *x, int64_t n_per_batch, int nbatch, const double *center, int power,
+                             int nblk, bool f64, double *partials, hipStream_t stream) {
+    dim3 grid(nblk, nbatch);
+    if (f64)
+        hipLaunchKernelGGL((block_sums_kernel<double>), grid, dim3(256), 0, stream, static_cast<const double *>(x),
+                           n_per_batch, center, power, partials);
+    else
+        hipLaunchKernelGGL((block_sums_kernel<float>), grid, dim3(256), 0, stream, static_cast<const float *>(x),
+                           n_per_batch, center, power, partials);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(const double *partials, int nblk, double scale, double *out) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) acc += partials[(int64_t)b * nblk + i];
+    const double tot = block_tree_sum(acc, red);
+    if (threadIdx.x == 0) out[b] = scale * tot;
+}
+
+hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(nbatch), dim3(256), 0, stream, partials, nblk, scale, out);
+    return hipGetLastError();
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void l2_loss_kernel(const Real *__restrict__ I, const Real *__restrict__ It,
+                                                      Real *__restrict__ grad, int64_t n, double *partials) {
+    __shared__ double red[256];
+    const int b = blockIdx.y, nblk = gridDim.x;
+    const int64_t off = (int64_t)b * n;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
+        const Real d = I[off + i] - It[off + i];
+        if (grad) grad[off + i] = (Real)2 * d;
+        acc += (double)d * (double)d;
+    }
+    const double tot = block_tree_sum(acc, red);
+    if (threadIdx.x == 0) partials[(int64_t)b * nblk + blockIdx.x] = tot;
+}
+
+hipError_t launch_l2_loss(const void *I, const void *It, void *grad, int64_t n_per_batch, int nbatch, int nblk,
+                          bool f64, double *partials, hipStream_t stream) {
+    dim3 grid(nblk, nbatch);
+    if (f64)
+        hipLaunchKernelGGL((l2_loss_kernel<double>), grid, dim3(256), 0, stream, static_cast<const double *>(I),
+                           static_cast<const double *>(It), static_cast<double *>(grad), n_per_batch, partials);
+    else
+        hipLaunchKernelGGL((l2_loss_kernel<float>), grid, dim3(256), 0, stream, static_cast<const float *>(I),
+                           static_cast<const float *>(It), static_cast<float *>(grad), n_per_batch, partials);
+    return hipGetLastError();
+}
+
+}  // namespace scint

@@ -1,0 +1,223 @@
+// device_common.hpp -- complex arithmetic, compile-time trigonometry, the
+// in-register radix butterflies and the Philox4x32-10 counter generator used
+// by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scint {
+
+template <typename Real> struct alignas(2 * sizeof(Real)) cpx {
+    Real re, im;
+};
+
+template <typename Real> __device__ __forceinline__ cpx<Real> cadd(cpx<Real> a, cpx<Real> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename Real> __device__ __forceinline__ cpx<Real> csub(cpx<Real> a, cpx<Real> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+template <typename Real> __device__ __forceinline__ cpx<Real> cmul(cpx<Real> a, cpx<Real> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename Real> __device__ __forceinline__ cpx<Real> cmulc(cpx<Real> a, cpx<Real> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename Real> __device__ __forceinline__ cpx<Real> cscale(cpx<Real> a, Real s) {
+    return {a.re * s, a.im * s};
+}
+// multiply by S*i (S = +1 or -1)
+template <int S, typename Real> __device__ __forceinline__ cpx<Real> mul_si(cpx<Real> a) {
+    if constexpr (S > 0) return {-a.im, a.re};
+    else return {a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time cos/sin of 2 pi n / d.  Exact rational octant reduction to an
+// angle of at most pi/4, then Taylor series in double (error below 1 ulp).
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+    double term = x, sum = x, x2 = x * x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double term = 1.0, sum = 1.0, x2 = x * x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+
+struct SinCos {
+    double c, s;
+};
+
+// cos and sin of 2 pi n/d for integers (any sign of n), d > 0.
+constexpr SinCos sincos2pi(long long n, long long d) {
+    long long m = n % d;
+    if (m < 0) m += d;
+    // angle = 2 pi m/d, m/d in [0,1)
+    double sign_s = 1.0;
+    long long num = m, den = d;
+    if (2 * num > den) {  // r > 1/2: r -> 1 - r, sin flips
+        num = den - num;
+        sign_s = -1.0;
+    }
+    // now r = num/den in [0, 1/2]
+    double sign_c = 1.0;
+    if (4 * num > den) {  // r > 1/4: r -> 1/2 - r, cos flips
+        num = den - 2 * num;
+        den = 2 * den;
+        sign_c = -1.0;
+    }
+    // r in [0, 1/4]
+    bool swap = false;
+    if (8 * num > den) {  // r > 1/8: r -> 1/4 - r, swap sin and cos
+        num = den - 4 * num;
+        den = 4 * den;
+        swap = true;
+    }
+    double x = 2.0 * kPi * (double)num / (double)den;
+    double c = taylor_cos(x), s = taylor_sin(x);
+    if (swap) {
+        double t = c;
+        c = s;
+        s = t;
+    }
+    return SinCos{sign_c * c, sign_s * s};
+}
+
+// Table of W_R^{e} = exp(S 2 pi i e / R), e in [0, R), built at compile time.
+template <int R, int S> struct RootTable {
+    double c[R], s[R];
+    constexpr RootTable() : c(), s() {
+        for (int e = 0; e < R; ++e) {
+            SinCos v = sincos2pi((long long)S * e, R);
+            c[e] = v.c;
+            s[e] = v.s;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// In-register DFT of size R:  a[k] <- sum_n a[n] exp(S 2 pi i n k / R).
+// Base radices 2, 4, 5; larger radices by one Cooley-Tukey split R = R1 R2
+// (decimation in time) with compile-time twiddles.
+// ---------------------------------------------------------------------------
+template <int R> constexpr int split_factor() {
+    if constexpr (R % 4 == 0 && R != 8) return 4;
+    else if constexpr (R % 2 == 0) return 2;
+    else return 5;
+}
+
+template <int R, int S, typename Real> struct Dft;
+
+template <int S, typename Real> struct Dft<1, S, Real> {
+    static __device__ __forceinline__ void run(cpx<Real>*) {}
+};
+
+template <int S, typename Real> struct Dft<2, S, Real> {
+    static __device__ __forceinline__ void run(cpx<Real>* a) {
+        cpx<Real> t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    }
+};
+
+template <int S, typename Real> struct Dft<4, S, Real> {
+    static __device__ __forceinline__ void run(cpx<Real>* a) {
+        cpx<Real> s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+        cpx<Real> s13 = cadd(a[1], a[3]), d13 = mul_si<S>(csub(a[1], a[3]));
+        a[0] = cadd(s02, s13);
+        a[2] = csub(s02, s13);
+        a[1] = cadd(d02, d13);
+        a[3] = csub(d02, d13);
+    }
+};
+
+template <int S, typename Real> struct Dft<5, S, Real> {
+    static __device__ __forceinline__ void run(cpx<Real>* a) {
+        constexpr SinCos w1 = sincos2pi(1, 5), w2 = sincos2pi(2, 5);
+        const Real c1 = (Real)w1.c, c2 = (Real)w2.c;
+        const Real s1 = (Real)(S * w1.s), s2 = (Real)(S * w2.s);
+        cpx<Real> b1 = cadd(a[1], a[4]), b4 = csub(a[1], a[4]);
+        cpx<Real> b2 = cadd(a[2], a[3]), b3 = csub(a[2], a[3]);
+        cpx<Real> x0 = a[0];
+        a[0] = cadd(x0, cadd(b1, b2));
+        // real-coefficient parts
+        cpx<Real> p1 = {x0.re + c1 * b1.re + c2 * b2.re, x0.im + c1 * b1.im + c2 * b2.im};
+        cpx<Real> p2 = {x0.re + c2 * b1.re + c1 * b2.re, x0.im + c2 * b1.im + c1 * b2.im};
+        // i * (s1 b4 + s2 b3) and i * (s2 b4 - s1 b3)
+        Real q1re = s1 * b4.re + s2 * b3.re, q1im = s1 * b4.im + s2 * b3.im;
+        Real q2re = s2 * b4.re - s1 * b3.re, q2im = s2 * b4.im - s1 * b3.im;
+        a[1] = {p1.re - q1im, p1.im + q1re};
+        a[4] = {p1.re + q1im, p1.im - q1re};
+        a[2] = {p2.re - q2im, p2.im + q2re};
+        a[3] = {p2.re + q2im, p2.im - q2re};
+    }
+};
+
+template <int R, int S, typename Real> struct Dft {
+    static constexpr int R1 = split_factor<R>();
+    static constexpr int R2 = R / R1;
+    static __device__ __forceinline__ void run(cpx<Real>* a) {
+        constexpr RootTable<R, S> W{};
+        cpx<Real> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            cpx<Real> b[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) b[n1] = a[R2 * n1 + n2];
+            Dft<R1, S, Real>::run(b);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int e = (n2 * k1) % R;
+                if (e == 0) {
+                    y[n2 * R1 + k1] = b[k1];
+                } else {
+                    cpx<Real> w = {(Real)W.c[e], (Real)W.s[e]};
+                    y[n2 * R1 + k1] = cmul(b[k1], w);
+                }
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cpx<Real> c[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) c[n2] = y[n2 * R1 + k1];
+            Dft<R2, S, Real>::run(c);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = c[k2];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// ---------------------------------------------------------------------------
+struct U32x4 {
+    uint32_t x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x0), lo0 = 0xD2511F53u * c.x0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.x2), lo1 = 0xCD9E8D57u * c.x2;
+        c = U32x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+}  // namespace scint

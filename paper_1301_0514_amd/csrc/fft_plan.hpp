@@ -1,0 +1,96 @@
+// fft_plan.hpp -- compile-time Stockham plans for the 1-D transforms along a
+// row of the N x N grid.  Included by the kernels (which unroll the stages)
+// and by the host (which builds the per-stage twiddle tables from the same
+// description).
+//
+// A length-L transform is done by T = L/E threads; each thread keeps E
+// elements in registers, namely x[t + m T] for m in [0, E).  Stage s has radix
+// R_s (R_s divides E, so each thread does E/R_s butterflies of it), and Ns is
+// the product of the radices of the earlier stages.  Butterfly j of stage s
+// takes x[j + r L/R_s] (r < R_s), multiplies by W_{Ns R_s}^{r (j mod Ns)},
+// does an R_s-point DFT and writes to (j - j mod Ns) R_s + j mod Ns + r Ns:
+// the self-sorting (Stockham) order, so the result ends in natural order with
+// every thread again holding x[t + m T].
+#pragma once
+
+namespace scint {
+
+template <int L> struct Plan;  // only the sizes below exist
+
+#define SCINT_PLAN(L_, E_, ...)                                                 \
+    template <> struct Plan<L_> {                                               \
+        static constexpr int L = L_;                                            \
+        static constexpr int E = E_;                                            \
+        static constexpr int R[] = {__VA_ARGS__};                               \
+        static constexpr int NS = sizeof(R) / sizeof(int);                      \
+        static constexpr int T = L_ / E_;                                       \
+    };
+
+// powers of two
+SCINT_PLAN(16, 16, 16)
+SCINT_PLAN(32, 8, 8, 4)
+SCINT_PLAN(64, 8, 8, 8)
+SCINT_PLAN(128, 16, 16, 8)
+SCINT_PLAN(256, 16, 16, 16)
+SCINT_PLAN(512, 8, 8, 8, 8)
+SCINT_PLAN(1024, 16, 16, 16, 4)
+SCINT_PLAN(2048, 16, 16, 16, 8)
+SCINT_PLAN(4096, 16, 16, 16, 16)
+SCINT_PLAN(8192, 16, 16, 16, 16, 2)
+SCINT_PLAN(16384, 32, 16, 16, 16, 4)
+// 2^a 5^b
+SCINT_PLAN(40, 20, 4, 10)
+SCINT_PLAN(80, 20, 4, 20)
+SCINT_PLAN(100, 10, 10, 10)
+SCINT_PLAN(160, 20, 4, 4, 10)
+SCINT_PLAN(200, 20, 20, 10)
+SCINT_PLAN(320, 20, 4, 4, 20)
+SCINT_PLAN(400, 20, 20, 20)
+SCINT_PLAN(640, 20, 4, 4, 4, 10)
+SCINT_PLAN(1000, 10, 10, 10, 10)
+SCINT_PLAN(1280, 20, 4, 4, 4, 20)
+SCINT_PLAN(2000, 20, 20, 10, 10)
+SCINT_PLAN(2560, 20, 4, 4, 4, 4, 10)
+SCINT_PLAN(4000, 20, 20, 20, 10)
+SCINT_PLAN(5000, 10, 10, 10, 10, 5)
+SCINT_PLAN(8000, 20, 20, 20, 20)
+SCINT_PLAN(10000, 10, 10, 10, 10, 10)
+
+#undef SCINT_PLAN
+
+// Sizes in ascending order, per precision (FP64 stops at 8192 because a
+// 16384-point complex128 row does not fit in the 160 KB of LDS).
+#define SCINT_SIZES_F64(X)                                                      \
+    X(16) X(32) X(40) X(64) X(80) X(100) X(128) X(160) X(200) X(256) X(320)     \
+    X(400) X(512) X(640) X(1000) X(1024) X(1280) X(2000) X(2048) X(2560)        \
+    X(4000) X(4096) X(5000) X(8000) X(8192)
+#define SCINT_SIZES_F32(X) SCINT_SIZES_F64(X) X(10000) X(16384)
+
+// Number of entries of the per-stage twiddle tables of a plan: stage s >= 1
+// holds W_{Ns R}^{r k} for k < Ns and r < R, i.e. Ns R entries.
+template <int L> constexpr int twiddle_count() {
+    int n = 0, ns = 1;
+    for (int s = 0; s < Plan<L>::NS; ++s) {
+        if (s > 0) n += ns * Plan<L>::R[s];
+        ns *= Plan<L>::R[s];
+    }
+    return n;
+}
+
+// Offset of stage s's table inside the concatenated twiddle array.
+template <int L> constexpr int twiddle_offset(int stage) {
+    int n = 0, ns = 1;
+    for (int s = 0; s < stage; ++s) {
+        if (s > 0) n += ns * Plan<L>::R[s];
+        ns *= Plan<L>::R[s];
+    }
+    return n;
+}
+
+template <int L> constexpr int stage_ns(int stage) {
+    int ns = 1;
+    for (int s = 0; s < stage; ++s) ns *= Plan<L>::R[s];
+    return ns;
+}
+
+}  // namespace scint

@@ -1,0 +1,381 @@
+// row_kernel.hpp -- the row-pass kernel: one or more rows of length N per
+// workgroup, kept in registers, transformed by a Stockham FFT whose stages
+// exchange data through LDS, and driven by a RowProgram.
+#pragma once
+
+#include "device_common.hpp"
+#include "fft_plan.hpp"
+#include "row_program.h"
+
+namespace scint {
+
+// LDS layout of a row: one padding slot every 16 elements breaks the
+// power-of-two strides of the Stockham writes across banks.
+constexpr int kLdsPadShift = 4;
+__device__ __forceinline__ int lds_index(int p) { return p + (p >> kLdsPadShift); }
+
+template <typename Real, int L> struct RowCfg {
+    using P = Plan<L>;
+    static constexpr int T = P::T;
+    static constexpr int LDS_STRIDE = L + (L >> kLdsPadShift);
+    static constexpr int ELEM = 2 * (int)sizeof(Real);
+    static constexpr int B_THREADS = T >= 256 ? 1 : 256 / T;
+    static constexpr int B_LDS = (P::NS > 1) ? ((65536 / (LDS_STRIDE * ELEM)) > 0 ? 65536 / (LDS_STRIDE * ELEM) : 1)
+                                             : B_THREADS;
+    static constexpr int B = B_THREADS < B_LDS ? B_THREADS : B_LDS;  // rows per workgroup
+    static constexpr int THREADS = T * B;
+    // LDS: the FFT exchange buffers, or at least one double per thread for
+    // the row reductions.
+    static constexpr int FFT_LDS_BYTES = (P::NS > 1) ? B * LDS_STRIDE * ELEM : 0;
+    static constexpr int RED_LDS_BYTES = THREADS * 8;
+    static constexpr int LDS_BYTES = FFT_LDS_BYTES > RED_LDS_BYTES ? FFT_LDS_BYTES : RED_LDS_BYTES;
+    // lower bound on the occupancy the register allocator must keep: two
+    // waves per SIMD (up to 256 VGPRs), which the heaviest programs need
+    // without spilling; lighter programs use fewer registers anyway
+    static constexpr int WAVES_PER_EU = 2;
+};
+
+// ---------------------------------------------------------------- FFT
+template <typename Real, int L, int s>
+__device__ __forceinline__ void fft_stage(cpx<Real> (&v)[Plan<L>::E], cpx<Real> *lds, int t,
+                                          const cpx<Real> *__restrict__ tw) {
+    using P = Plan<L>;
+    constexpr int E = P::E, T = P::T, R = P::R[s], Q = E / R;
+    constexpr int Ns = stage_ns<L>(s);
+    constexpr bool last = (s == P::NS - 1);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int j = t + i * T;
+        const int k = (Ns == 1) ? 0 : (j % Ns);
+        cpx<Real> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = v[i + r * Q];
+        if constexpr (Ns > 1) {
+            // keep the compiler from hoisting twiddle loads out of loops over
+            // wavelengths (they would stay live in registers across FFTs)
+            asm volatile("" ::: "memory");
+            const cpx<Real> *w = tw + twiddle_offset<L>(s) + k * R;
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
+        }
+        Dft<R, -1, Real>::run(a);
+        if constexpr (last) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i + r * Q] = a[r];
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_index(base + r * Ns)] = a[r];
+        }
+    }
+    if constexpr (!last) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = lds[lds_index(t + m * T)];
+        __syncthreads();
+        fft_stage<Real, L, s + 1>(v, lds, t, tw);
+    }
+}
+
+// Forward DFT of the register row (natural order in, natural order out).
+template <typename Real, int L>
+__device__ __forceinline__ void fft_forward(cpx<Real> (&v)[Plan<L>::E], cpx<Real> *lds, int t,
+                                            const cpx<Real> *__restrict__ tw) {
+    fft_stage<Real, L, 0>(v, lds, t, tw);
+}
+
+// ---------------------------------------------------------------- pointwise
+// exp(2 pi i turns) with the argument reduced to [-1/2, 1/2] in FP64 and the
+// sine/cosine evaluated in the working precision.
+template <typename Real> __device__ __forceinline__ cpx<Real> expi_turns(double turns);
+template <> __device__ __forceinline__ cpx<float> expi_turns<float>(double turns) {
+    const double f = turns - rint(turns);
+    float s, c;
+    sincospif((float)(2.0 * f), &s, &c);
+    return {c, s};
+}
+template <> __device__ __forceinline__ cpx<double> expi_turns<double>(double turns) {
+    const double f = turns - rint(turns);
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    return {c, s};
+}
+
+// Random phase spectrum coefficient at Fourier pixel (kx, ky) of realisation r.
+template <typename Real>
+__device__ __forceinline__ cpx<Real> spectrum_coeff(int kx, int ky, int N, uint32_t r,
+                                                    const RowProgram &p);
+
+template <>
+__device__ __forceinline__ cpx<float> spectrum_coeff<float>(int kx, int ky, int N, uint32_t r,
+                                                            const RowProgram &p) {
+    const U32x4 w = philox4x32_10(U32x4{(uint32_t)kx, (uint32_t)ky, r, 0u}, p.seed_lo, p.seed_hi);
+    const uint64_t a = ((uint64_t)w.x0 << 32) | w.x1;
+    const uint64_t b = ((uint64_t)w.x2 << 32) | w.x3;
+    const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
+    const float rad = sqrtf(-2.0f * logf((float)u1));
+    float sn, cs;
+    sincospif((float)(2.0 * (u2 - rint(u2))), &sn, &cs);
+    const int fx = kx < N / 2 ? kx : kx - N;
+    const int fy = ky < N / 2 ? ky : ky - N;
+    const uint32_t k2 = (uint32_t)(fx * fx) + (uint32_t)(fy * fy);
+    if (k2 == 0u) return {0.0f, 0.0f};
+    // amp = amp0 k2^(-beta/4): log2 of the mantissa in FP32, the product with
+    // -beta/4 in FP64, exp2 of the fractional part in FP32.
+    int ex;
+    const float mant = frexpf((float)k2, &ex);
+    const double y = p.neg_beta_4 * ((double)ex + (double)log2f(mant));
+    const double n = floor(y);
+    const float amp = ldexpf((float)p.amp0 * exp2f((float)(y - n)), (int)n) * 0.70710678118654752f;
+    return {amp * rad * cs, amp * rad * sn};
+}
+
+template <>
+__device__ __forceinline__ cpx<double> spectrum_coeff<double>(int kx, int ky, int N, uint32_t r,
+                                                              const RowProgram &p) {
+    const U32x4 w = philox4x32_10(U32x4{(uint32_t)kx, (uint32_t)ky, r, 0u}, p.seed_lo, p.seed_hi);
+    const uint64_t a = ((uint64_t)w.x0 << 32) | w.x1;
+    const uint64_t b = ((uint64_t)w.x2 << 32) | w.x3;
+    const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * (u2 - rint(u2)), &sn, &cs);
+    const int fx = kx < N / 2 ? kx : kx - N;
+    const int fy = ky < N / 2 ? ky : ky - N;
+    const double k2 = (double)fx * fx + (double)fy * fy;
+    if (k2 == 0.0) return {0.0, 0.0};
+    const double amp = p.amp0 * pow(k2, p.neg_beta_4) * 0.70710678118654752440;
+    return {amp * rad * cs, amp * rad * sn};
+}
+
+template <typename Real> __device__ __forceinline__ Real sqrt2_of() { return (Real)1.41421356237309504880; }
+
+// ---------------------------------------------------------------- kernel
+// A row program's op codes are a compile-time list (so each program is
+// straight-line code with exact register liveness); its operands (pointers,
+// strides, scales) come at run time in the RowProgram, op[i] matching code i.
+template <int... C> struct OpList {
+    static constexpr int code[] = {C...};
+    static constexpr int n = sizeof...(C);
+};
+
+template <class Ops> constexpr int find_endloop(int i) {
+    for (int j = i; j < Ops::n; ++j)
+        if (Ops::code[j] == ROP_ENDLOOP) return j;
+    return Ops::n;
+}
+
+template <typename Real, int L> struct RowState {
+    static constexpr int E = Plan<L>::E;
+    cpx<Real> v[E];
+    Real acc[E];
+    Real keep[E];
+    cpx<Real> keepc[E];
+    const RowProgram *prog;
+    cpx<Real> *lds;
+    const cpx<Real> *tw;
+    double *red;
+    int t, tid, g, batch, row, it;
+    bool valid;
+};
+
+template <typename Real, int L, int CODE>
+__device__ __forceinline__ void exec_op(RowState<Real, L> &st, const RowOp &op) {
+    constexpr int E = Plan<L>::E, T = Plan<L>::T;
+    auto &v = st.v;
+    const bool valid = st.valid;
+    const int64_t off = (int64_t)st.batch * op.batch_stride + (int64_t)st.it * op.iter_stride +
+                        (int64_t)st.row * op.row_stride + st.t;
+    const double s = (op.flags & RF_ITER_SCALE) ? st.prog->scale[st.it] : op.param;
+    if constexpr (CODE == ROP_LOAD_C) {
+        const cpx<Real> *src = static_cast<const cpx<Real> *>(op.ptr) + off;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = valid ? src[m * T] : cpx<Real>{(Real)0, (Real)0};
+    } else if constexpr (CODE == ROP_LOAD_R) {
+        const Real *src = static_cast<const Real *>(op.ptr) + off;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = {valid ? src[m * T] : (Real)0, (Real)0};
+    } else if constexpr (CODE == ROP_LOAD_PHASE) {
+        const Real *src = static_cast<const Real *>(op.ptr) + off;
+        const double sturn = s * (0.5 / kPi);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)(valid ? src[m * T] : (Real)0));
+    } else if constexpr (CODE == ROP_NOISE) {
+        const uint32_t r = (uint32_t)st.prog->r0 + (uint32_t)st.batch;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = spectrum_coeff<Real>(st.row, st.t + m * T, L, r, *st.prog);
+    } else if constexpr (CODE == ROP_KEEP_R) {
+        const Real *src = static_cast<const Real *>(op.ptr) + off;
+#pragma unroll
+        for (int m = 0; m < E; ++m) st.keep[m] = valid ? src[m * T] : (Real)0;
+    } else if constexpr (CODE == ROP_EXP_KEEP) {
+        const double sturn = s * (0.5 / kPi);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)st.keep[m]);
+    } else if constexpr (CODE == ROP_FFT_FWD) {
+        fft_forward<Real, L>(v, st.lds, st.t, st.tw);
+    } else if constexpr (CODE == ROP_FFT_INV) {
+        // IDFT(v) = conj(DFT(conj(v)))
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
+        fft_forward<Real, L>(v, st.lds, st.t, st.tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
+    } else if constexpr (CODE == ROP_MUL_TAB) {
+        const cpx<Real> *tab = static_cast<const cpx<Real> *>(op.ptr) + off;
+        if (op.flags & RF_CONJ) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = cmulc(v[m], tab[m * T]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = cmul(v[m], tab[m * T]);
+        }
+    } else if constexpr (CODE == ROP_MUL_RTAB2D) {
+        const Real *tab = static_cast<const Real *>(op.ptr) + off;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cscale(v[m], tab[m * T]);
+    } else if constexpr (CODE == ROP_MUL_RLOAD) {
+        const Real *src = static_cast<const Real *>(op.ptr) + off;
+        const Real sc = (Real)op.param;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cscale(v[m], sc * (valid ? src[m * T] : (Real)0));
+    } else if constexpr (CODE == ROP_SQRT2RE) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = {sqrt2_of<Real>() * v[m].re, (Real)0};
+    } else if constexpr (CODE == ROP_EXP_RE) {
+        const double sturn = s * (0.5 / kPi);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)v[m].re);
+    } else if constexpr (CODE == ROP_STORE_C) {
+        if (valid && op.ptr != nullptr) {
+            cpx<Real> *dst = static_cast<cpx<Real> *>(const_cast<void *>(op.ptr)) + off;
+#pragma unroll
+            for (int m = 0; m < E; ++m) dst[m * T] = v[m];
+        }
+    } else if constexpr (CODE == ROP_STORE_R) {
+        if (valid && op.ptr != nullptr) {
+            Real *dst = static_cast<Real *>(const_cast<void *>(op.ptr)) + off;
+            const Real sc = (Real)op.param;
+#pragma unroll
+            for (int m = 0; m < E; ++m) dst[m * T] = sc * v[m].re;
+        }
+    } else if constexpr (CODE == ROP_ACC_ABS2) {
+        const Real w = (Real)((op.flags & RF_ITER_WEIGHT) ? st.prog->weight[st.it] : op.param);
+#pragma unroll
+        for (int m = 0; m < E; ++m) st.acc[m] += w * (v[m].re * v[m].re + v[m].im * v[m].im);
+    } else if constexpr (CODE == ROP_STORE_ACC) {
+        if (valid) {
+            Real *dst = static_cast<Real *>(const_cast<void *>(op.ptr)) + off;
+            if (op.flags & RF_ADD) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) dst[m * T] += st.acc[m];
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; ++m) dst[m * T] = st.acc[m];
+            }
+        }
+    } else if constexpr (CODE == ROP_SAVE) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) st.keepc[m] = v[m];
+    } else if constexpr (CODE == ROP_RESTORE) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = st.keepc[m];
+    } else if constexpr (CODE == ROP_GRAD_PHI) {
+        const Real *src = static_cast<const Real *>(op.ptr) + off;
+        const double sturn = s * (0.5 / kPi);
+        const Real sc = (Real)s;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const cpx<Real> u = expi_turns<Real>(sturn * (double)(valid ? src[m * T] : (Real)0));
+            v[m] = {sc * (v[m].im * u.re - v[m].re * u.im), (Real)0};  // s Im(v conj(u))
+        }
+    } else if constexpr (CODE == ROP_DOT_R) {
+        // per-row sum of src[e] Re v[e] in FP64 in a fixed order: registers,
+        // then a tree over the row's threads through LDS
+        const Real *src = static_cast<const Real *>(op.ptr) + off;
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < E; ++m) part += (double)(valid ? src[m * T] : (Real)0) * (double)v[m].re;
+        double *red = st.red;
+        __syncthreads();
+        red[st.tid] = part;
+        __syncthreads();
+        for (int width = 1; width < T; width *= 2) {
+            if ((st.t % (2 * width)) == 0 && st.t + width < T) red[st.tid] += red[st.tid + width];
+            __syncthreads();
+        }
+        if (st.t == 0 && valid) static_cast<double *>(op.ptr2)[st.g] = red[st.tid];
+        __syncthreads();
+    } else {
+        static_assert(CODE == ROP_END, "unknown row op");
+    }
+}
+
+template <typename Real, int L, class Ops, int I, int End>
+__device__ __forceinline__ void run_ops(RowState<Real, L> &st) {
+    if constexpr (I < End) {
+        constexpr int c = Ops::code[I];
+        if constexpr (c == ROP_LOOP) {
+            constexpr int e = find_endloop<Ops>(I);
+#pragma clang loop unroll(disable)
+            for (st.it = 0; st.it < st.prog->n_iter; ++st.it) run_ops<Real, L, Ops, I + 1, e>(st);
+            st.it = 0;
+            run_ops<Real, L, Ops, e + 1, End>(st);
+        } else {
+            exec_op<Real, L, c>(st, st.prog->op[I]);
+            run_ops<Real, L, Ops, I + 1, End>(st);
+        }
+    }
+}
+
+template <typename Real, int L, class Ops>
+__global__ __launch_bounds__((RowCfg<Real, L>::THREADS))
+__attribute__((amdgpu_waves_per_eu(RowCfg<Real, L>::WAVES_PER_EU))) void row_kernel(const RowProgram prog,
+                                                                        const cpx<Real> *__restrict__ tw) {
+    using Cfg = RowCfg<Real, L>;
+    constexpr int E = Plan<L>::E, T = Plan<L>::T, B = Cfg::B;
+    __shared__ __align__(16) unsigned char lds_raw[Cfg::LDS_BYTES];
+    RowState<Real, L> st;
+    st.prog = &prog;
+    st.tid = threadIdx.x;
+    const int bsub = st.tid / T;
+    st.t = st.tid - bsub * T;
+    st.g = blockIdx.x * B + bsub;  // global row over the batch
+    st.valid = st.g < prog.total_rows;
+    st.batch = st.valid ? st.g / L : 0;
+    st.row = st.valid ? st.g - st.batch * L : 0;
+    st.lds = reinterpret_cast<cpx<Real> *>(lds_raw) + bsub * Cfg::LDS_STRIDE;
+    st.red = reinterpret_cast<double *>(lds_raw);
+    st.tw = tw;
+    st.it = 0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        st.v[m] = {(Real)0, (Real)0};
+        st.acc[m] = (Real)0;
+    }
+    run_ops<Real, L, Ops, 0, Ops::n>(st);
+}
+
+// The row programs used by the library.  Each name lists its op codes; the
+// host fills the operands of op[i] for code i.
+using ProgNoise = OpList<ROP_NOISE, ROP_FFT_INV, ROP_STORE_C>;
+using ProgScreen = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R>;
+using ProgScreenProp = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R, ROP_EXP_RE, ROP_FFT_FWD,
+                              ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
+using ProgPhaseProp = OpList<ROP_KEEP_R, ROP_LOOP, ROP_EXP_KEEP, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV,
+                             ROP_STORE_C, ROP_ENDLOOP>;
+using ProgPropIntensity = OpList<ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_ACC_ABS2,
+                                 ROP_ENDLOOP, ROP_STORE_ACC>;
+using ProgRealFwd = OpList<ROP_LOAD_R, ROP_FFT_FWD, ROP_STORE_C>;
+using ProgFwdRe = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_STORE_R>;
+using ProgSmearMid = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_SAVE, ROP_LOOP, ROP_RESTORE, ROP_MUL_RTAB2D,
+                            ROP_FFT_INV, ROP_STORE_C, ROP_ENDLOOP>;
+using ProgInvRe = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_STORE_R>;
+using ProgVjpY = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_MUL_RLOAD, ROP_FFT_FWD,
+                        ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
+using ProgVjpX = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_GRAD_PHI, ROP_STORE_R,
+                        ROP_DOT_R>;
+
+}  // namespace scint

@@ -1,0 +1,86 @@
+// row_program.h -- the small program a row-pass kernel executes.  Plain data,
+// shared by the host (which builds programs) and the kernels (which run them).
+//
+// A row pass gives each row of a batch of N x N arrays to T = N/E threads that
+// keep the row in registers (element e = t + m T in register m).  The program
+// is a list of operations applied to that register row: loads (complex, real,
+// exp(i s phi), or the random phase spectrum), forward and inverse FFTs along
+// the row, pointwise multiplies (Fresnel chirp, disk spectrum, gradient),
+// and stores.  An optional loop repeats a range of operations n_iter times
+// (over wavelengths or source radii) with per-iteration pointer offsets,
+// phase scales and weights.
+#pragma once
+
+#include <stdint.h>
+
+namespace scint {
+
+enum RowOpCode : int32_t {
+    ROP_END = 0,
+    ROP_LOAD_C,      // v = src[e]                      (complex)
+    ROP_LOAD_R,      // v = (src[e], 0)                 (real)
+    ROP_LOAD_PHASE,  // v = exp(i s src[e])             (real phase; s = phase scale)
+    ROP_NOISE,       // v = random phase spectrum, row = kx, element = ky
+    ROP_KEEP_R,      // keep = src[e]                   (real, kept for ROP_EXP_KEEP)
+    ROP_EXP_KEEP,    // v = exp(i s keep)
+    ROP_FFT_FWD,     // v = DFT(v)   (kernel exp(-2 pi i e k / N))
+    ROP_FFT_INV,     // v = IDFT(v)  (kernel exp(+2 pi i e k / N), unnormalised)
+    ROP_MUL_TAB,     // v *= tab[e]  (complex table along the row; flag 1: conjugate)
+    ROP_MUL_RTAB2D,  // v *= tab[row][e]  (real 2-D table, no batch offset)
+    ROP_MUL_RLOAD,   // v *= param * src[e]  (real array)
+    ROP_SQRT2RE,     // v = (sqrt(2) Re v, 0)
+    ROP_EXP_RE,      // v = exp(i s Re v)
+    ROP_STORE_C,     // dst[e] = v
+    ROP_STORE_R,     // dst[e] = param * Re v
+    ROP_ACC_ABS2,    // acc += w |v|^2
+    ROP_STORE_ACC,   // dst[e] = acc   (flag 1: dst[e] += acc)
+    ROP_SAVE,        // keepc = v
+    ROP_RESTORE,     // v = keepc
+    ROP_GRAD_PHI,    // v = (s Im(v conj(exp(i s src[e]))), 0)   (src = phi)
+    ROP_DOT_R,       // ptr2[global row] = sum_e src[e] Re v   (double)
+    ROP_LOOP,        // start of the repeated range
+    ROP_ENDLOOP,     // end of the repeated range
+};
+
+// Flag bits
+enum : int32_t {
+    RF_CONJ = 1,       // ROP_MUL_TAB: multiply by the conjugate
+    RF_ADD = 1,        // ROP_STORE_ACC: accumulate into dst
+    RF_ITER_SCALE = 2, // phase scale s = scale[it] (else param)
+    RF_ITER_WEIGHT = 4 // ROP_ACC_ABS2: w = weight[it] (else param)
+};
+
+// Address of element e of row `row` of batch b at loop iteration it:
+//   ptr + b * batch_stride + it * iter_stride + row * row_stride + e
+// (strides in elements of the operand's type).
+struct RowOp {
+    int32_t code;
+    int32_t flags;
+    int64_t batch_stride;
+    int64_t iter_stride;
+    int64_t row_stride;
+    const void *ptr;
+    void *ptr2;      // ROP_DOT_R: double destination, one value per global row
+    double param;
+};
+
+constexpr int kRowMaxOps = 20;
+constexpr int kRowMaxIter = 64;
+
+struct RowProgram {
+    RowOp op[kRowMaxOps];
+    int32_t n_iter;      // iterations of the loop range (>= 1)
+    int32_t N;           // row length (= grid size)
+    int32_t total_rows;  // batch * N
+    int32_t r0;          // realisation of batch 0 (ROP_NOISE)
+    uint32_t seed_lo, seed_hi;
+    double amp0;         // sqrt(C_beta R^(2-beta)) N^(beta/2) / N   (ROP_NOISE)
+    double neg_beta_4;   // -beta/4                                 (ROP_NOISE)
+    double scale[kRowMaxIter];
+    double weight[kRowMaxIter];
+};
+
+// Feature sets: which register arrays beyond the row itself a kernel keeps.
+enum RowFeature : int { RFEAT_PLAIN = 0, RFEAT_KEEP = 1, RFEAT_ACC = 2, RFEAT_KEEPC = 4 };
+
+}  // namespace scint

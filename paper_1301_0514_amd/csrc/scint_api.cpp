@@ -1,0 +1,828 @@
+// scint_api.cpp -- the C ABI declared in include/scint.h: argument
+// validation, per-device caches (twiddle tables, disk spectra), per-stream
+// workspace, and the sequence of passes behind each entry point.
+//
+// Every 2-D transform is a row pass, a batched transpose and a second row
+// pass; the pointwise steps of the method are fused into the row passes:
+//   screen:      [noise -> IDFT along ky] T [IDFT along kx -> sqrt2 Re]
+//   propagation: [exp(i s phi) -> DFT_x -> H1 -> IDFT_x] T
+//                [DFT_y -> H1 -> IDFT_y -> |.|^2 (sum over wavelengths)] T
+// The spectrum is generated with rows indexed by kx so that the first pass
+// runs along ky; the transposes leave every output in natural [y][x] order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/scint.h"
+#include "aux_kernels.h"
+#include "fft_plan.hpp"
+#include "row_launch.h"
+
+using namespace scint;
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local std::string g_last_warning;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(PS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr double kPiD = 3.141592653589793238462643383279502884;
+
+bool supported_f64(int N) {
+    switch (N) {
+#define SCINT_CASE(LL) case LL:
+        SCINT_SIZES_F64(SCINT_CASE)
+#undef SCINT_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+bool supported_f32(int N) {
+    switch (N) {
+#define SCINT_CASE(LL) case LL:
+        SCINT_SIZES_F32(SCINT_CASE)
+#undef SCINT_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+std::vector<int> size_list(int dtype) {
+    std::vector<int> v;
+#define SCINT_CASE(LL) v.push_back(LL);
+    if (dtype == PS_F64) {
+        SCINT_SIZES_F64(SCINT_CASE)
+    } else {
+        SCINT_SIZES_F32(SCINT_CASE)
+    }
+#undef SCINT_CASE
+    std::sort(v.begin(), v.end());
+    return v;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_common(int N, int dtype, int n) {
+    if (dtype != PS_F32 && dtype != PS_F64) return fail(PS_E_DTYPE, "dtype must be PS_F32 or PS_F64");
+    if (!(dtype == PS_F64 ? supported_f64(N) : supported_f32(N)))
+        return fail(PS_E_SIZE, "unsupported grid size N=" + std::to_string(N) + " for this dtype");
+    if (n < 1) return fail(PS_E_SIZE, "batch count must be >= 1");
+    // bound the number of rows so that every row index fits an int
+    if ((int64_t)n * N > (int64_t)1 << 30) return fail(PS_E_SIZE, "batch too large");
+    return PS_OK;
+}
+
+size_t real_bytes(int dtype) { return dtype == PS_F64 ? 8 : 4; }
+
+// true if [a, a+na) and [b, b+nb) overlap
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+// ------------------------------------------------------------ device caches
+struct DeviceCache {
+    std::map<std::pair<int, int>, void *> twiddles;  // (L, dtype) -> table
+    std::map<std::tuple<int, uint64_t, int>, void *> disks;  // (N, radius bits, dtype) -> spectrum
+    std::map<hipStream_t, std::pair<void *, size_t>> workspace;
+};
+
+std::mutex g_mutex;
+std::map<int, DeviceCache> g_cache;
+
+int current_device(int *dev) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    return PS_OK;
+}
+
+// Twiddle table of the length-L plan in the working precision.
+int get_twiddles(int L, int dtype, const void **out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto &dc = g_cache[dev];
+    auto key = std::make_pair(L, dtype);
+    auto it = dc.twiddles.find(key);
+    if (it != dc.twiddles.end()) {
+        *out = it->second;
+        return PS_OK;
+    }
+    const int n = twiddle_entries(L);
+    std::vector<double> ri(2 * (size_t)std::max(n, 1));
+    if (n > 0 && !build_twiddles(L, ri.data())) return fail(PS_E_SIZE, "no FFT plan for this size");
+    const size_t bytes = 2 * real_bytes(dtype) * (size_t)std::max(n, 1);
+    void *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of twiddle table failed");
+    hipError_t e;
+    if (dtype == PS_F64) {
+        e = hipMemcpy(d, ri.data(), bytes, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> f(ri.size());
+        for (size_t i = 0; i < ri.size(); ++i) f[i] = (float)ri[i];
+        e = hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(PS_E_DEVICE, std::string("hipMemcpy twiddles: ") + hipGetErrorString(e));
+    }
+    dc.twiddles[key] = d;
+    *out = d;
+    return PS_OK;
+}
+
+// Workspace of at least `bytes` for this device and stream.
+int get_workspace(hipStream_t stream, size_t bytes, void **out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto &ws = g_cache[dev].workspace[stream];
+    if (ws.second < bytes) {
+        if (ws.first) {
+            // work queued on this stream may still use the old buffer
+            HIP_TRY(hipStreamSynchronize(stream));
+            (void)hipFree(ws.first);
+            ws.first = nullptr;
+            ws.second = 0;
+        }
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        if (hipMalloc(&ws.first, want) != hipSuccess) {
+            ws.first = nullptr;
+            return fail(PS_E_ALLOC, "hipMalloc of " + std::to_string(want) + " workspace bytes failed");
+        }
+        ws.second = want;
+    }
+    *out = ws.first;
+    return PS_OK;
+}
+
+// Carves aligned sub-buffers out of one workspace allocation.
+struct Carver {
+    size_t used = 0;
+    size_t take(size_t bytes) {
+        size_t off = used;
+        used += (bytes + 255) & ~(size_t)255;
+        return off;
+    }
+};
+
+// ------------------------------------------------------------ row programs
+struct ProgBuilder {
+    RowProgram p;
+    int n = 0;
+    ProgBuilder(int N, int64_t total_rows) {
+        std::memset(&p, 0, sizeof(p));
+        p.N = N;
+        p.total_rows = (int32_t)total_rows;
+        p.n_iter = 1;
+        for (int i = 0; i < kRowMaxIter; ++i) {
+            p.scale[i] = 1.0;
+            p.weight[i] = 1.0;
+        }
+    }
+    ProgBuilder &op(int code, const void *ptr = nullptr, int64_t batch_stride = 0, int64_t row_stride = 0,
+                    int64_t iter_stride = 0, int flags = 0, double param = 0.0, void *ptr2 = nullptr) {
+        RowOp &o = p.op[n++];
+        o.code = code;
+        o.ptr = ptr;
+        o.ptr2 = ptr2;
+        o.batch_stride = batch_stride;
+        o.row_stride = row_stride;
+        o.iter_stride = iter_stride;
+        o.flags = flags;
+        o.param = param;
+        return *this;
+    }
+};
+
+template <class Tag> int run_row(int dtype, int N, const RowProgram &p, hipStream_t stream) {
+    const void *tw = nullptr;
+    if (int rc = get_twiddles(N, dtype, &tw)) return rc;
+    hipError_t e = dtype == PS_F64 ? launch_row<double, Tag>(N, p, tw, stream)
+                                   : launch_row<float, Tag>(N, p, tw, stream);
+    if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("row pass launch: ") + hipGetErrorString(e));
+    return PS_OK;
+}
+
+int transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes, hipStream_t stream) {
+    HIP_TRY(launch_transpose(in, out, N, nbatch, elem_bytes, stream));
+    return PS_OK;
+}
+
+// Chirp tables H1(k)/N for n wavelengths with Fresnel radii rho[j] pixels.
+int chirp_tables(void *tab, int N, const std::vector<double> &rho, int dtype, bool normalise, hipStream_t stream) {
+    const int n = (int)rho.size();
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        const int m = std::min(64, n - j0);
+        double a[64];
+        for (int j = 0; j < m; ++j) a[j] = kPiD * rho[j0 + j] * rho[j0 + j] / ((double)N * (double)N);
+        char *base = static_cast<char *>(tab) + (size_t)j0 * N * 2 * real_bytes(dtype);
+        HIP_TRY(launch_chirp_tables(base, N, a, m, normalise ? 1.0 / N : 1.0, dtype == PS_F64, stream));
+    }
+    return PS_OK;
+}
+
+double f_beta(double beta) { return std::pow(2.0, -beta) * beta * std::tgamma(-beta / 2.0) / std::tgamma(beta / 2.0); }
+
+// Fills the noise operands: amp0 = sqrt(C_beta R^(2-beta)) N^(beta/2) / N.
+void set_noise(RowProgram &p, int N, double R, double beta, uint64_t seed, uint32_t r0) {
+    const double c_beta = 1.0 / (2.0 * std::pow(2.0 * kPiD, beta - 1.0) * f_beta(beta));
+    p.amp0 = std::sqrt(c_beta * std::pow(R, 2.0 - beta)) * std::pow((double)N, beta / 2.0) / (double)N;
+    p.neg_beta_4 = -beta / 4.0;
+    p.seed_lo = (uint32_t)(seed & 0xFFFFFFFFull);
+    p.seed_hi = (uint32_t)(seed >> 32);
+    p.r0 = (int32_t)r0;
+}
+
+int64_t nn(int N) { return (int64_t)N * N; }
+
+// Upper bound on workspace bytes a call plans for (whole-batch processing is
+// split into chunks above it).
+size_t workspace_budget() {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return (size_t)8 << 30;
+    const size_t cap = (size_t)48 << 30;
+    return std::min(cap, free_b / 2);
+}
+
+// ------------------------------------------------------------ pipelines
+// Screen of nb realisations into phi (and optionally through the
+// propagation into I).  W1/W2: complex [nb][N][N] workspaces.
+int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int nb, int dtype, void *W1, void *W2,
+                  hipStream_t stream) {
+    ProgBuilder a(N, (int64_t)nb * N);
+    set_noise(a.p, N, R, beta, seed, r0);
+    a.op(ROP_NOISE).op(ROP_FFT_INV).op(ROP_STORE_C, W1, nn(N), N);
+    if (int rc = run_row<ProgNoiseTag>(dtype, N, a.p, stream)) return rc;
+    return transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream);
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+int ps_version(void) { return 10000; }
+
+const char *ps_last_error(void) { return g_last_error.c_str(); }
+const char *ps_last_warning(void) { return g_last_warning.c_str(); }
+
+int ps_supported_size(int N, int dtype) {
+    if (dtype == PS_F64) return supported_f64(N) ? 1 : 0;
+    if (dtype == PS_F32) return supported_f32(N) ? 1 : 0;
+    return 0;
+}
+
+int ps_num_supported_sizes(int dtype) {
+    if (dtype != PS_F32 && dtype != PS_F64) return 0;
+    return (int)size_list(dtype).size();
+}
+
+int ps_supported_size_at(int dtype, int i) {
+    if (dtype != PS_F32 && dtype != PS_F64) return 0;
+    auto v = size_list(dtype);
+    return (i >= 0 && i < (int)v.size()) ? v[i] : 0;
+}
+
+int ps_release_cache(void) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    for (auto &kv : g_cache) {
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        for (auto &t : kv.second.twiddles) (void)hipFree(t.second);
+        for (auto &d : kv.second.disks) (void)hipFree(d.second);
+        for (auto &w : kv.second.workspace)
+            if (w.second.first) (void)hipFree(w.second.first);
+    }
+    g_cache.clear();
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return PS_OK;
+}
+
+int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed, uint32_t first_realisation,
+                int n_real, int dtype, void *phi_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n_real)) return rc;
+    if (!phi_out) return fail(PS_E_NULL, "phi_out is NULL");
+    if (!finite_pos(delta) || !finite_pos(r_diff)) return fail(PS_E_PARAM, "delta and r_diff must be finite and > 0");
+    if (!(std::isfinite(beta) && beta > 2.0 && beta < 4.0)) return fail(PS_E_PARAM, "beta must lie in (2, 4)");
+    if (delta >= r_diff / 2.0) g_last_warning = "pixel side >= R_diff/2: the phase variations are undersampled";
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    for (int b0 = 0; b0 < n_real; b0 += nb_max) {
+        const int nb = std::min(nb_max, n_real - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + 512, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        if (int rc = screen_passes(N, r_diff / delta, beta, seed, first_realisation + (uint32_t)b0, nb, dtype, W1,
+                                   W2, stream))
+            return rc;
+        ProgBuilder b(N, (int64_t)nb * N);
+        char *phi = static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        b.op(ROP_LOAD_C, W2, nn(N), N).op(ROP_FFT_INV).op(ROP_SQRT2RE).op(ROP_STORE_R, phi, nn(N), N, 0, 0, 1.0);
+        if (int rc = run_row<ProgScreenTag>(dtype, N, b.p, stream)) return rc;
+    }
+    return PS_OK;
+}
+
+int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t seed, uint32_t first_realisation,
+                      int n_real, double lambda, double z, int dtype, void *phi_out, void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n_real)) return rc;
+    if (!I_out) return fail(PS_E_NULL, "I_out is NULL");
+    if (!finite_pos(delta) || !finite_pos(r_diff) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, r_diff, lambda and z must be finite and > 0");
+    if (!(std::isfinite(beta) && beta > 2.0 && beta < 4.0)) return fail(PS_E_PARAM, "beta must lie in (2, 4)");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n_real;
+    if (phi_out && overlaps(phi_out, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "phi_out overlaps I_out");
+    if (delta >= r_diff / 2.0) g_last_warning = "pixel side >= R_diff/2: the phase variations are undersampled";
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    for (int b0 = 0; b0 < n_real; b0 += nb_max) {
+        const int nb = std::min(nb_max, n_real - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        void *H = base + c.take(tbytes);
+        if (int rc = chirp_tables(H, N, {rho}, dtype, true, stream)) return rc;
+        if (int rc = screen_passes(N, r_diff / delta, beta, seed, first_realisation + (uint32_t)b0, nb, dtype, W1,
+                                   W2, stream))
+            return rc;
+        char *phi = phi_out ? static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype) : nullptr;
+        ProgBuilder b(N, (int64_t)nb * N);
+        b.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_INV)
+            .op(ROP_SQRT2RE)
+            .op(ROP_STORE_R, phi, nn(N), N, 0, 0, 1.0)
+            .op(ROP_EXP_RE, nullptr, 0, 0, 0, 0, 1.0)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H)
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, W1, nn(N), N);
+        if (int rc = run_row<ProgScreenPropTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
+        ProgBuilder d(N, (int64_t)nb * N);
+        d.op(ROP_LOOP)
+            .op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H)
+            .op(ROP_FFT_INV)
+            .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0)
+            .op(ROP_ENDLOOP)
+            .op(ROP_STORE_ACC, W1, nn(N), N);
+        if (int rc = run_row<ProgPropIntensityTag>(dtype, N, d.p, stream)) return rc;
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
+    return PS_OK;
+}
+
+// Propagation of nb screens for a chunk of wavelengths: intensities summed
+// with the given weights into Iacc (transposed layout [b][x][y]); add != 0
+// accumulates onto Iacc.
+static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> &rho,
+                      const std::vector<double> &scale, const std::vector<double> &weight, int dtype, void *W1,
+                      void *W2, void *H, void *Iacc, bool add, hipStream_t stream) {
+    const int C = (int)rho.size();
+    if (int rc = chirp_tables(H, N, rho, dtype, true, stream)) return rc;
+    ProgBuilder a(N, (int64_t)nb * N);
+    a.p.n_iter = C;
+    for (int j = 0; j < C; ++j) a.p.scale[j] = scale[j];
+    a.op(ROP_KEEP_R, phi, nn(N), N)
+        .op(ROP_LOOP)
+        .op(ROP_EXP_KEEP, nullptr, 0, 0, 0, RF_ITER_SCALE)
+        .op(ROP_FFT_FWD)
+        .op(ROP_MUL_TAB, H, 0, 0, N)
+        .op(ROP_FFT_INV)
+        .op(ROP_STORE_C, W1, nn(N), N, (int64_t)nb * nn(N))
+        .op(ROP_ENDLOOP);
+    if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, stream)) return rc;
+    if (int rc = transpose(W1, W2, N, (int64_t)nb * C, 2 * (int)real_bytes(dtype), stream)) return rc;
+    ProgBuilder b(N, (int64_t)nb * N);
+    b.p.n_iter = C;
+    for (int j = 0; j < C; ++j) b.p.weight[j] = weight[j];
+    b.op(ROP_LOOP)
+        .op(ROP_LOAD_C, W2, nn(N), N, (int64_t)nb * nn(N))
+        .op(ROP_FFT_FWD)
+        .op(ROP_MUL_TAB, H, 0, 0, N)
+        .op(ROP_FFT_INV)
+        .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, RF_ITER_WEIGHT)
+        .op(ROP_ENDLOOP)
+        .op(ROP_STORE_ACC, Iacc, nn(N), N, 0, add ? RF_ADD : 0);
+    return run_row<ProgPropIntensityTag>(dtype, N, b.p, stream);
+}
+
+int fresnel_propagate(int N, double delta, double lambda, double z, const void *phi, double phase_scale, int n,
+                      int dtype, void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
+    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        void *H = base + c.take(tbytes);
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        // W1 (complex) is free again once transposed into W2, so it holds the
+        // transposed intensity
+        if (int rc = poly_chunk(N, ph, nb, {rho}, {phase_scale}, {1.0}, dtype, W1, W2, H, W1, false, stream))
+            return rc;
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
+    return PS_OK;
+}
+
+int illumination_polychromatic(int N, double delta, double z, const void *phi_ref, double lambda_ref,
+                               const double *lambdas, const double *weights, int n_lambda, int n_real, int dtype,
+                               void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n_real)) return rc;
+    if (!phi_ref || !I_out || !lambdas) return fail(PS_E_NULL, "phi_ref, lambdas and I_out must be non-NULL");
+    if (n_lambda < 1 || n_lambda > 4096) return fail(PS_E_SIZE, "n_lambda must lie in [1, 4096]");
+    if (!finite_pos(delta) || !finite_pos(z) || !finite_pos(lambda_ref))
+        return fail(PS_E_PARAM, "delta, z and lambda_ref must be finite and > 0");
+    double wsum = 0.0;
+    for (int j = 0; j < n_lambda; ++j) {
+        if (!finite_pos(lambdas[j])) return fail(PS_E_PARAM, "every wavelength must be finite and > 0");
+        const double w = weights ? weights[j] : 1.0;
+        if (!std::isfinite(w) || w < 0.0) return fail(PS_E_PARAM, "weights must be finite and >= 0");
+        wsum += w;
+    }
+    if (!(wsum > 0.0)) return fail(PS_E_PARAM, "weights must have a positive sum");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n_real;
+    if (overlaps(phi_ref, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi_ref");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::vector<double> rho(n_lambda), scale(n_lambda), weight(n_lambda);
+    for (int j = 0; j < n_lambda; ++j) {
+        rho[j] = std::sqrt(lambdas[j] * z / (2.0 * kPiD)) / delta;
+        scale[j] = lambda_ref / lambdas[j];
+        weight[j] = (weights ? weights[j] : 1.0) / wsum;
+    }
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
+    const size_t budget = workspace_budget();
+    // wavelengths per pass C (<= 64) and realisations per pass nb so that two
+    // complex buffers of C*nb grids plus the accumulator fit the budget
+    int C = std::min(n_lambda, kRowMaxIter);
+    while (C > 1 && 2 * cbytes * (size_t)C + rb1 > budget) C = (C + 1) / 2;
+    const int nb_max = (int)std::max<size_t>(1, budget / (2 * cbytes * (size_t)C + rb1));
+    for (int b0 = 0; b0 < n_real; b0 += nb_max) {
+        const int nb = std::min(nb_max, n_real - b0);
+        void *ws = nullptr;
+        const size_t tbytes = (size_t)C * N * 2 * real_bytes(dtype);
+        if (int rc = get_workspace(stream, 2 * cbytes * (size_t)C * nb + rb1 * nb + tbytes + 2048, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * (size_t)C * nb);
+        void *W2 = base + c.take(cbytes * (size_t)C * nb);
+        void *Iacc = base + c.take(rb1 * nb);
+        void *H = base + c.take(tbytes);
+        const char *ph = static_cast<const char *>(phi_ref) + (size_t)b0 * rb1;
+        for (int j0 = 0; j0 < n_lambda; j0 += C) {
+            const int m = std::min(C, n_lambda - j0);
+            std::vector<double> r(rho.begin() + j0, rho.begin() + j0 + m);
+            std::vector<double> s(scale.begin() + j0, scale.begin() + j0 + m);
+            std::vector<double> w(weight.begin() + j0, weight.begin() + j0 + m);
+            if (int rc = poly_chunk(N, ph, nb, r, s, w, dtype, W1, W2, H, Iacc, j0 > 0, stream)) return rc;
+        }
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * rb1;
+        if (int rc = transpose(Iacc, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
+    return PS_OK;
+}
+
+// Spectrum of the normalised disk of radius R pixels, divided by N^2 (the
+// inverse-transform normalisation), as a real N x N table indexed [kx][ky].
+static int get_disk_spectrum(int N, double Rpx, int dtype, hipStream_t stream, const void **out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    uint64_t bits;
+    std::memcpy(&bits, &Rpx, sizeof(bits));
+    auto key = std::make_tuple(N, bits, dtype);
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        auto &dc = g_cache[dev];
+        auto it = dc.disks.find(key);
+        if (it != dc.disks.end()) {
+            *out = it->second;
+            return PS_OK;
+        }
+    }
+    // pixel count of the disk, same test as the disk image kernel
+    const double r2 = Rpx * Rpx;
+    double count = 0.0;
+    for (int y = 0; y < N; ++y) {
+        const double dy = y < N / 2 ? y : y - N;
+        if (dy * dy > r2) continue;
+        for (int x = 0; x < N; ++x) {
+            const double dx = x < N / 2 ? x : x - N;
+            if (dx * dx + dy * dy <= r2) count += 1.0;
+        }
+    }
+    const size_t rb = (size_t)nn(N) * real_bytes(dtype);
+    const size_t cb = 2 * rb;
+    void *tab = nullptr;
+    if (hipMalloc(&tab, rb) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of disk spectrum failed");
+    void *tmp = nullptr;
+    if (hipMalloc(&tmp, 2 * cb) != hipSuccess) {
+        (void)hipFree(tab);
+        return fail(PS_E_ALLOC, "hipMalloc of disk workspace failed");
+    }
+    char *W1 = static_cast<char *>(tmp), *W2 = W1 + cb;
+    int rc = PS_OK;
+    hipError_t e = launch_disk_image(tab, N, r2, 1.0 / count, dtype == PS_F64, stream);
+    if (e != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk image: ") + hipGetErrorString(e));
+    if (!rc) {
+        ProgBuilder a(N, N);
+        a.op(ROP_LOAD_R, tab, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, 0, N);
+        rc = run_row<ProgRealFwdTag>(dtype, N, a.p, stream);
+    }
+    if (!rc) rc = transpose(W1, W2, N, 1, 2 * (int)real_bytes(dtype), stream);
+    if (!rc) {
+        ProgBuilder b(N, N);
+        b.op(ROP_LOAD_C, W2, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_R, tab, 0, N, 0, 0, 1.0 / (double)nn(N));
+        rc = run_row<ProgFwdReTag>(dtype, N, b.p, stream);
+    }
+    if (!rc) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk spectrum: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(tmp);
+    if (rc) {
+        (void)hipFree(tab);
+        return rc;
+    }
+    std::lock_guard<std::mutex> lock(g_mutex);
+    g_cache[dev].disks[key] = tab;
+    *out = tab;
+    return PS_OK;
+}
+
+int source_smear(int N, double delta, const void *I_in, const double *radii, int n_r, int n_real, int dtype,
+                 void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n_real)) return rc;
+    if (!I_in || !I_out || !radii) return fail(PS_E_NULL, "I_in, radii and I_out must be non-NULL");
+    if (n_r < 1 || n_r > kRowMaxIter) return fail(PS_E_SIZE, "n_r must lie in [1, 64]");
+    if (!finite_pos(delta)) return fail(PS_E_PARAM, "delta must be finite and > 0");
+    for (int j = 0; j < n_r; ++j)
+        if (!std::isfinite(radii[j]) || radii[j] < 0.0) return fail(PS_E_PARAM, "radii must be finite and >= 0");
+    const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
+    if (overlaps(I_in, rb1 * n_real, I_out, rb1 * n_real * n_r) && !(n_r == 1 && I_in == I_out))
+        return fail(PS_E_ALIAS, "I_out overlaps I_in (allowed only in place with n_r == 1)");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::vector<const void *> disk(n_r);
+    for (int j = 0; j < n_r; ++j)
+        if (int rc = get_disk_spectrum(N, radii[j] / delta, dtype, stream, &disk[j])) return rc;
+    // the loop over radii indexes the disk tables through iter_stride, so
+    // they must be equally spaced; copy them into one block when they are not
+    const size_t cbytes = 2 * rb1;
+    const size_t budget = workspace_budget();
+    const int nb_max = (int)std::max<size_t>(1, (budget > rb1 * n_r ? budget - rb1 * n_r : 0) /
+                                                    (cbytes * (2 + 2 * (size_t)n_r)));
+    for (int b0 = 0; b0 < n_real; b0 += nb_max) {
+        const int nb = std::min(nb_max, n_real - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, cbytes * nb * (2 + 2 * (size_t)n_r) + rb1 * n_r + 4096, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        char *D = base + c.take(rb1 * n_r);
+        char *W1 = base + c.take(cbytes * nb);
+        char *W2 = base + c.take(cbytes * nb);
+        char *V1 = base + c.take(cbytes * nb * n_r);
+        char *V2 = base + c.take(cbytes * nb * n_r);
+        for (int j = 0; j < n_r; ++j)
+            HIP_TRY(hipMemcpyAsync(D + j * rb1, disk[j], rb1, hipMemcpyDeviceToDevice, stream));
+        const char *Iin = static_cast<const char *>(I_in) + (size_t)b0 * rb1;
+        ProgBuilder a(N, (int64_t)nb * N);
+        a.op(ROP_LOAD_R, Iin, nn(N), N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, nn(N), N);
+        if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
+        ProgBuilder b(N, (int64_t)nb * N);
+        b.p.n_iter = n_r;
+        b.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_SAVE)
+            .op(ROP_LOOP)
+            .op(ROP_RESTORE)
+            .op(ROP_MUL_RTAB2D, D, 0, N, nn(N))
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, V1, (int64_t)n_r * nn(N), N, nn(N))
+            .op(ROP_ENDLOOP);
+        if (int rc = run_row<ProgSmearMidTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = transpose(V1, V2, N, (int64_t)nb * n_r, (int)(cbytes / nn(N)), stream)) return rc;
+        ProgBuilder d(N, (int64_t)nb * n_r * N);
+        char *Iout = static_cast<char *>(I_out) + (size_t)b0 * n_r * rb1;
+        d.op(ROP_LOAD_C, V2, nn(N), N).op(ROP_FFT_INV).op(ROP_STORE_R, Iout, nn(N), N, 0, 0, 1.0);
+        if (int rc = run_row<ProgInvReTag>(dtype, N, d.p, stream)) return rc;
+    }
+    return PS_OK;
+}
+
+int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const void *phi, double phase_scale,
+                          const void *grad_I, int n, int dtype, void *grad_phi_out, double *phi_dot_grad_out,
+                          void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !grad_I || !grad_phi_out) return fail(PS_E_NULL, "phi, grad_I and grad_phi_out must be non-NULL");
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
+    if (overlaps(grad_phi_out, rb1 * n, phi, rb1 * n) || overlaps(grad_phi_out, rb1 * n, grad_I, rb1 * n))
+        return fail(PS_E_ALIAS, "grad_phi_out overlaps phi or grad_I");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const size_t cbytes = 2 * rb1;
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes + rb1 + N * 8));
+    std::vector<double> dots(n, 0.0);
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        void *ws = nullptr;
+        const int nblk_rows = 1;
+        (void)nblk_rows;
+        if (int rc = get_workspace(stream, (2 * cbytes + rb1) * nb + tbytes + (size_t)nb * N * 8 + nb * 8 + 4096,
+                                   &ws))
+            return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        char *W1 = base + c.take(cbytes * nb);
+        char *W2 = base + c.take(cbytes * nb);
+        char *Gt = base + c.take(rb1 * nb);
+        char *H = base + c.take(tbytes);
+        double *rowdot = reinterpret_cast<double *>(base + c.take((size_t)nb * N * 8));
+        double *bdot = reinterpret_cast<double *>(base + c.take((size_t)nb * 8));
+        if (int rc = chirp_tables(H, N, {rho}, dtype, true, stream)) return rc;
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * rb1;
+        const char *gI = static_cast<const char *>(grad_I) + (size_t)b0 * rb1;
+        // forward x-propagation (recomputed; nothing is kept between calls)
+        ProgBuilder a(N, (int64_t)nb * N);
+        a.op(ROP_KEEP_R, ph, nn(N), N)
+            .op(ROP_LOOP)
+            .op(ROP_EXP_KEEP, nullptr, 0, 0, 0, 0, phase_scale)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H)
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, W1, nn(N), N)
+            .op(ROP_ENDLOOP);
+        if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
+        if (int rc = transpose(gI, Gt, N, nb, (int)real_bytes(dtype), stream)) return rc;
+        // y-propagation to A (transposed), g_A = 2 grad_I A, adjoint y-propagation
+        ProgBuilder b(N, (int64_t)nb * N);
+        b.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H)
+            .op(ROP_FFT_INV)
+            .op(ROP_MUL_RLOAD, Gt, nn(N), N, 0, 0, 2.0)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H, 0, 0, 0, RF_CONJ)
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, W1, nn(N), N);
+        if (int rc = run_row<ProgVjpYTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
+        // adjoint x-propagation, dL/dphi = s Im(g_U conj U), and sum phi dL/dphi per row
+        char *gphi = static_cast<char *>(grad_phi_out) + (size_t)b0 * rb1;
+        ProgBuilder d(N, (int64_t)nb * N);
+        d.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H, 0, 0, 0, RF_CONJ)
+            .op(ROP_FFT_INV)
+            .op(ROP_GRAD_PHI, ph, nn(N), N, 0, 0, phase_scale)
+            .op(ROP_STORE_R, gphi, nn(N), N, 0, 0, 1.0)
+            .op(ROP_DOT_R, ph, nn(N), N, 0, 0, 0.0, rowdot);
+        if (int rc = run_row<ProgVjpXTag>(dtype, N, d.p, stream)) return rc;
+        if (phi_dot_grad_out) {
+            HIP_TRY(launch_finalize_sums(rowdot, N, nb, 1.0, bdot, stream));
+            HIP_TRY(hipMemcpyAsync(dots.data() + b0, bdot, (size_t)nb * 8, hipMemcpyDeviceToHost, stream));
+        }
+    }
+    if (phi_dot_grad_out) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        std::memcpy(phi_dot_grad_out, dots.data(), (size_t)n * 8);
+    }
+    return PS_OK;
+}
+
+static int block_count(int64_t n) {
+    const int64_t per = 256 * 16;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + per - 1) / per));
+}
+
+int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out, double *mean_out,
+                        void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!I || !m_out) return fail(PS_E_NULL, "I and m_out must be non-NULL");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t per = nn(N);
+    const int nblk = block_count(per);
+    void *ws = nullptr;
+    if (int rc = get_workspace(stream, (size_t)n * nblk * 8 + (size_t)n * 16 + 1024, &ws)) return rc;
+    Carver c;
+    char *base = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(base + c.take((size_t)n * nblk * 8));
+    double *mean = reinterpret_cast<double *>(base + c.take((size_t)n * 8));
+    double *var = reinterpret_cast<double *>(base + c.take((size_t)n * 8));
+    const bool f64 = dtype == PS_F64;
+    HIP_TRY(launch_block_sums(I, per, n, nullptr, 1, nblk, f64, part, stream));
+    HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0 / (double)per, mean, stream));
+    HIP_TRY(launch_block_sums(I, per, n, mean, 2, nblk, f64, part, stream));
+    HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0 / (double)per, var, stream));
+    std::vector<double> hm(n), hv(n);
+    HIP_TRY(hipMemcpyAsync(hm.data(), mean, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(hv.data(), var, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (int b = 0; b < n; ++b) {
+        m_out[b] = std::sqrt(hv[b]) / hm[b];
+        if (mean_out) mean_out[b] = hm[b];
+    }
+    return PS_OK;
+}
+
+int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype, void *grad_out, double *loss_out,
+               void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!I || !I_target) return fail(PS_E_NULL, "I and I_target must be non-NULL");
+    const size_t rb = (size_t)nn(N) * real_bytes(dtype) * n;
+    if (grad_out && (overlaps(grad_out, rb, I, rb) || overlaps(grad_out, rb, I_target, rb)))
+        return fail(PS_E_ALIAS, "grad_out overlaps I or I_target");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t per = nn(N);
+    const int nblk = block_count(per);
+    void *ws = nullptr;
+    if (int rc = get_workspace(stream, (size_t)n * nblk * 8 + (size_t)n * 8 + 1024, &ws)) return rc;
+    Carver c;
+    char *base = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(base + c.take((size_t)n * nblk * 8));
+    double *tot = reinterpret_cast<double *>(base + c.take((size_t)n * 8));
+    HIP_TRY(launch_l2_loss(I, I_target, grad_out, per, n, nblk, dtype == PS_F64, part, stream));
+    if (loss_out) {
+        HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0, tot, stream));
+        std::vector<double> h(n);
+        HIP_TRY(hipMemcpyAsync(h.data(), tot, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        std::memcpy(loss_out, h.data(), (size_t)n * 8);
+    }
+    return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// twiddles.cpp -- host construction of the per-stage twiddle tables of the
+// Stockham plans, evaluated in extended precision and rounded once by the
+// caller to the working precision.
+#include <cmath>
+#include <cstddef>
+
+#include "fft_plan.hpp"
+#include "row_launch.h"
+
+namespace scint {
+
+// exp(-2 pi i m / M) with exact integer reduction of m modulo M and an octant
+// reduction of the angle, in long double.
+static void root_ld(long long m, long long M, long double &c, long double &s) {
+    m %= M;
+    if (m < 0) m += M;
+    long long num = m, den = M;
+    long double sign_s = 1.0L, sign_c = 1.0L;
+    if (2 * num > den) {
+        num = den - num;
+        sign_s = -1.0L;
+    }
+    if (4 * num > den) {
+        num = den - 2 * num;
+        den *= 2;
+        sign_c = -1.0L;
+    }
+    bool swap = false;
+    if (8 * num > den) {
+        num = den - 4 * num;
+        den *= 4;
+        swap = true;
+    }
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double x = 2.0L * pi * (long double)num / (long double)den;
+    long double cc = cosl(x), ss = sinl(x);
+    if (swap) {
+        long double t = cc;
+        cc = ss;
+        ss = t;
+    }
+    c = sign_c * cc;
+    s = -sign_s * ss;  // forward transform: exp(-i angle)
+}
+
+template <int L> static void fill(double *out) {
+    using P = Plan<L>;
+    long long ns = 1;
+    size_t idx = 0;
+    for (int st = 0; st < P::NS; ++st) {
+        const long long R = P::R[st];
+        if (st > 0) {
+            for (long long k = 0; k < ns; ++k)
+                for (long long r = 0; r < R; ++r) {
+                    long double c, s;
+                    root_ld(r * k, ns * R, c, s);
+                    out[2 * idx] = (double)c;
+                    out[2 * idx + 1] = (double)s;
+                    ++idx;
+                }
+        }
+        ns *= R;
+    }
+}
+
+int twiddle_entries(int L) {
+#define SCINT_CASE(LL) \
+    case LL:           \
+        return twiddle_count<LL>();
+    switch (L) {
+        SCINT_SIZES_F32(SCINT_CASE)
+    default:
+        return 0;
+    }
+#undef SCINT_CASE
+}
+
+bool build_twiddles(int L, double *out) {
+#define SCINT_CASE(LL)  \
+    case LL:            \
+        fill<LL>(out);  \
+        return true;
+    switch (L) {
+        SCINT_SIZES_F32(SCINT_CASE)
+    default:
+        return false;
+    }
+#undef SCINT_CASE
+}
+
+}  // namespace scint

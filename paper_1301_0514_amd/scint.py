@@ -1,0 +1,277 @@
+"""ctypes binding of libscint.so (the C ABI in include/scint.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libscint.so.  PyTorch supplies device memory and the current HIP
+stream.  If the library has not been built this module raises on import of
+the library (no CPU fallback exists).
+
+Function names and argument order follow the C ABI; arrays are torch tensors
+on the current GPU, contiguous, float32 (PS_F32) or float64 (PS_F64).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libscint.so")
+
+PS_F32, PS_F64 = 0, 1
+PS_OK = 0
+STATUS_NAMES = {0: "PS_OK", -1: "PS_E_NULL", -2: "PS_E_SIZE", -3: "PS_E_PARAM", -4: "PS_E_DTYPE",
+                -5: "PS_E_ALLOC", -6: "PS_E_DEVICE", -7: "PS_E_ALIAS", -8: "PS_E_UNIMPLEMENTED"}
+
+# Every symbol include/scint.h declares, with its ctypes signature.
+_c_int, _c_dbl, _c_u32, _c_u64, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "ps_supported_size": (_c_int, [_c_int, _c_int]),
+    "ps_num_supported_sizes": (_c_int, [_c_int]),
+    "ps_supported_size_at": (_c_int, [_c_int, _c_int]),
+    "ps_generate": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _c_u64, _c_u32, _c_int, _c_int, _vp, _vp]),
+    "fresnel_propagate": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_int, _c_int, _vp, _vp]),
+    "ps_screen_fresnel": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _c_u64, _c_u32, _c_int, _c_dbl, _c_dbl,
+                                   _c_int, _vp, _vp, _vp]),
+    "illumination_polychromatic": (_c_int, [_c_int, _c_dbl, _c_dbl, _vp, _c_dbl, _dp, _dp, _c_int, _c_int,
+                                            _c_int, _vp, _vp]),
+    "source_smear": (_c_int, [_c_int, _c_dbl, _vp, _dp, _c_int, _c_int, _c_int, _vp, _vp]),
+    "fresnel_propagate_vjp": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _vp, _c_int, _c_int,
+                                       _vp, _dp, _vp]),
+    "ps_modulation_index": (_c_int, [_c_int, _vp, _c_int, _c_int, _dp, _dp, _vp]),
+    "ps_l2_loss": (_c_int, [_c_int, _vp, _vp, _c_int, _c_int, _vp, _dp, _vp]),
+    "ps_last_error": (ctypes.c_char_p, []),
+    "ps_last_warning": (ctypes.c_char_p, []),
+    "ps_release_cache": (_c_int, []),
+    "ps_version": (_c_int, []),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class ScintError(RuntimeError):
+    """A libscint entry point returned a non-OK status."""
+
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__("%s returned %s (%d): %s" % (fn, STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load libscint.so (built by paper_1301_0514_amd.build) and bind every
+    symbol of include/scint.h.  Raises FileNotFoundError if it is not built."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise FileNotFoundError("libscint.so not built: run `python -m paper_1301_0514_amd.build` (%s)" % p)
+        lib = ctypes.CDLL(p)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def _check(fn: str, rc: int) -> None:
+    if rc != PS_OK:
+        raise ScintError(fn, rc, load_library().ps_last_error().decode())
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float32:
+        return PS_F32
+    if t == torch.float64:
+        return PS_F64
+    raise TypeError("libscint works on float32 or float64 tensors, got %s" % t)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _host_doubles(vals):
+    arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+def _batch_of(t: torch.Tensor, N: int) -> int:
+    if t.dim() < 2 or t.shape[-1] != N or t.shape[-2] != N:
+        raise ValueError("expected a [..., N, N] tensor with N=%d, got %s" % (N, tuple(t.shape)))
+    return t.numel() // (N * N)
+
+
+# ------------------------------------------------------------------ queries
+def supported_size(N: int, dtype: torch.dtype = torch.float32) -> bool:
+    return bool(load_library().ps_supported_size(int(N), _dtype_code(dtype)))
+
+
+def supported_sizes(dtype: torch.dtype = torch.float32) -> list[int]:
+    lib = load_library()
+    code = _dtype_code(dtype)
+    return [lib.ps_supported_size_at(code, i) for i in range(lib.ps_num_supported_sizes(code))]
+
+
+def last_warning() -> str:
+    return load_library().ps_last_warning().decode()
+
+
+def release_cache() -> None:
+    _check("ps_release_cache", load_library().ps_release_cache())
+
+
+def version() -> int:
+    return load_library().ps_version()
+
+
+# ------------------------------------------------------------------ entry points
+def ps_generate(N, delta, r_diff, beta, seed, first_realisation=0, n_real=1, dtype=torch.float32,
+                out: torch.Tensor | None = None, device=None) -> torch.Tensor:
+    """Phase screens [n_real, N, N] (radians); see ps_generate in scint.h."""
+    device = torch.device(device or "cuda")
+    if out is None:
+        out = torch.empty((n_real, N, N), dtype=dtype, device=device)
+    rc = load_library().ps_generate(int(N), float(delta), float(r_diff), float(beta), int(seed),
+                                    int(first_realisation), int(n_real), _dtype_code(out.dtype),
+                                    _ptr(out), _stream(out.device))
+    _check("ps_generate", rc)
+    return out
+
+
+def fresnel_propagate(phi: torch.Tensor, delta, lam, z, phase_scale=1.0,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """Point-source illumination I = |A|^2 of each screen; see scint.h."""
+    N = phi.shape[-1]
+    n = _batch_of(phi, N)
+    if out is None:
+        out = torch.empty_like(phi)
+    rc = load_library().fresnel_propagate(int(N), float(delta), float(lam), float(z), _ptr(phi),
+                                          float(phase_scale), n, _dtype_code(phi.dtype), _ptr(out),
+                                          _stream(phi.device))
+    _check("fresnel_propagate", rc)
+    return out
+
+
+def ps_screen_fresnel(N, delta, r_diff, beta, seed, lam, z, first_realisation=0, n_real=1,
+                      dtype=torch.float32, want_phi=False, device=None):
+    """Screen generation and propagation fused; returns I (and phi if asked)."""
+    device = torch.device(device or "cuda")
+    I = torch.empty((n_real, N, N), dtype=dtype, device=device)
+    phi = torch.empty_like(I) if want_phi else None
+    rc = load_library().ps_screen_fresnel(int(N), float(delta), float(r_diff), float(beta), int(seed),
+                                          int(first_realisation), int(n_real), float(lam), float(z),
+                                          _dtype_code(dtype), _ptr(phi), _ptr(I), _stream(device))
+    _check("ps_screen_fresnel", rc)
+    return (I, phi) if want_phi else I
+
+
+def illumination_polychromatic(phi_ref: torch.Tensor, delta, z, lam_ref, lambdas, weights=None,
+                               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Co-added illumination over the wavelengths; see scint.h."""
+    N = phi_ref.shape[-1]
+    n = _batch_of(phi_ref, N)
+    if out is None:
+        out = torch.empty_like(phi_ref)
+    lam = _host_doubles(lambdas)
+    w = None if weights is None else _host_doubles(weights)
+    if w is not None and len(weights) != len(lambdas):
+        raise ValueError("weights and lambdas differ in length")
+    rc = load_library().illumination_polychromatic(int(N), float(delta), float(z), _ptr(phi_ref), float(lam_ref),
+                                                   lam, w, len(lambdas), n, _dtype_code(phi_ref.dtype),
+                                                   _ptr(out), _stream(phi_ref.device))
+    _check("illumination_polychromatic", rc)
+    return out
+
+
+def source_smear(I: torch.Tensor, delta, radii, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Extended-source patterns [n_real, n_r, N, N]; see scint.h."""
+    N = I.shape[-1]
+    n = _batch_of(I, N)
+    if out is None:
+        out = torch.empty((n, len(radii), N, N), dtype=I.dtype, device=I.device)
+    rc = load_library().source_smear(int(N), float(delta), _ptr(I), _host_doubles(radii), len(radii), n,
+                                     _dtype_code(I.dtype), _ptr(out), _stream(I.device))
+    _check("source_smear", rc)
+    return out
+
+
+def fresnel_propagate_vjp(phi: torch.Tensor, delta, lam, z, grad_I: torch.Tensor, phase_scale=1.0,
+                          out: torch.Tensor | None = None, want_dot=False):
+    """dL/dphi for dL/dI = grad_I; optionally also sum(phi * dL/dphi) per screen."""
+    N = phi.shape[-1]
+    n = _batch_of(phi, N)
+    if grad_I.shape != phi.shape or grad_I.dtype != phi.dtype:
+        raise ValueError("grad_I must match phi in shape and dtype")
+    if out is None:
+        out = torch.empty_like(phi)
+    dots = (ctypes.c_double * n)() if want_dot else None
+    rc = load_library().fresnel_propagate_vjp(int(N), float(delta), float(lam), float(z), _ptr(phi),
+                                              float(phase_scale), _ptr(grad_I), n, _dtype_code(phi.dtype),
+                                              _ptr(out), dots, _stream(phi.device))
+    _check("fresnel_propagate_vjp", rc)
+    return (out, [dots[i] for i in range(n)]) if want_dot else out
+
+
+def ps_modulation_index(I: torch.Tensor, want_mean=False):
+    """m = sigma_I / mean(I) per pattern (FP64 accumulation); synchronises."""
+    N = I.shape[-1]
+    n = _batch_of(I, N)
+    m = (ctypes.c_double * n)()
+    mean = (ctypes.c_double * n)()
+    rc = load_library().ps_modulation_index(int(N), _ptr(I), n, _dtype_code(I.dtype), m, mean,
+                                            _stream(I.device))
+    _check("ps_modulation_index", rc)
+    ms = [m[i] for i in range(n)]
+    return (ms, [mean[i] for i in range(n)]) if want_mean else ms
+
+
+def ps_l2_loss(I: torch.Tensor, I_target: torch.Tensor, want_grad=True):
+    """L = sum (I - I_t)^2 per pattern and dL/dI = 2 (I - I_t)."""
+    N = I.shape[-1]
+    n = _batch_of(I, N)
+    grad = torch.empty_like(I) if want_grad else None
+    loss = (ctypes.c_double * n)()
+    rc = load_library().ps_l2_loss(int(N), _ptr(I), _ptr(I_target), n, _dtype_code(I.dtype), _ptr(grad), loss,
+                                   _stream(I.device))
+    _check("ps_l2_loss", rc)
+    return [loss[i] for i in range(n)], grad
+
+
+# ------------------------------------------------------------------ autograd
+class FresnelIntensity(torch.autograd.Function):
+    """I = fresnel_propagate(phi) with the hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, phi, delta, lam, z, phase_scale):
+        ctx.save_for_backward(phi)
+        ctx.args = (delta, lam, z, phase_scale)
+        return fresnel_propagate(phi.contiguous(), delta, lam, z, phase_scale)
+
+    @staticmethod
+    def backward(ctx, grad_I):
+        (phi,) = ctx.saved_tensors
+        delta, lam, z, s = ctx.args
+        g = fresnel_propagate_vjp(phi.contiguous(), delta, lam, z, grad_I.contiguous(), s)
+        return g, None, None, None, None
+
+
+def fresnel_intensity(phi, delta, lam, z, phase_scale=1.0):
+    """Differentiable propagation: gradients flow to phi through the adjoint kernels."""
+    return FresnelIntensity.apply(phi, delta, lam, z, phase_scale)
