@@ -141,9 +141,11 @@ def test_screen_fresnel(S, oracle, dtype, N, R, rho):
         ref_phi = oracle.screen(N, R, 11 / 3, 1, b)
         check_field(phi[b], ref_phi, dtype)
         check_intensity(I[b], oracle.propagate(ref_phi, rho), dtype)
-    # the fused screen equals ps_generate's
+    # the fused screen equals ps_generate's up to the rounding of two
+    # differently scheduled kernels
     phi2 = host(S.ps_generate(N, 1.0, R, 11 / 3, 1, 0, 2, dtype))
-    assert np.array_equal(phi, phi2)
+    ulp = np.finfo(np.float64 if dtype == torch.float64 else np.float32).eps
+    assert np.abs(phi - phi2).max() <= 8 * ulp * np.abs(phi).max()
 
 
 # ------------------------------------------------------------------ polychromatic
