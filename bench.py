@@ -1,0 +1,309 @@
+#!/usr/bin/env python3
+"""Benchmark of the phase-screen + Fresnel propagation hot path on one MI355X.
+
+One step is the whole batched path on synthetic input: 8 phase screens of
+8192^2 pixels (Kolmogorov, R_diff = 30 px at 650 nm), each propagated at 32
+wavelengths spanning 400-900 nm (R_F = 90 px at 650 nm, R_F ~ sqrt(lambda),
+phase ~ 1/lambda), co-added, and smeared by uniform stellar disks of radius
+{0.5, 1, 2, 4} R_F.  The metric is grid points x wavelengths per second.
+
+Prints one JSON line on stdout; progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    """Hash of the kernel sources; ties a stored counter profile to a build."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1301_0514_amd", "csrc", "*"))):
+        if p.endswith((".hip", ".hpp", ".h", ".cpp")):
+            with open(p, "rb") as fh:
+                h.update(os.path.basename(p).encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
+    summary (profiles/traffic_*.txt), if it was taken on the current sources."""
+    want = source_hash()
+    for p in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt")):
+        vals = {}
+        with open(p) as fh:
+            for line in fh:
+                if "=" in line and not line.lstrip().startswith("#"):
+                    k, v = (t.strip() for t in line.split("=", 1))
+                    vals[k] = v
+        if vals.get("kernel") == kernel and vals.get("source_sha256") == want:
+            try:
+                return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures the single-GPU path only (one MI355X); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_1301_0514_amd import presets, scint
+
+    scint.load_library()  # raises if the HIP library is not built
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    cfg = presets.POLY_8192
+    N, n_real, lams, radii = cfg.N, cfg.n_real, cfg.lambdas, cfg.smear_radii
+    n_lam = len(lams)
+    phi = torch.empty((n_real, N, N), dtype=torch.float32, device=dev)
+    I_sum = torch.empty_like(phi)
+    I_ext = torch.empty((n_real, len(radii), N, N), dtype=torch.float32, device=dev)
+
+    def step():
+        scint.ps_generate(N, 1.0, cfg.R_ref, cfg.beta, cfg.seed, 0, n_real, out=phi)
+        scint.illumination_polychromatic(phi, 1.0, cfg.z, cfg.lam_ref, lams, out=I_sum)
+        scint.source_smear(I_sum, 1.0, radii, out=I_ext)
+
+    log("warmup %d steps (N=%d, %d screens, %d wavelengths, %d radii)" % (args.warmup, N, n_real, n_lam, len(radii)))
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    scint.timing_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rep = scint.timing_report()
+    scint.timing_enable(False)
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    units = float(N) * N * n_lam * n_real
+    value = units / (ms_step / 1e3)
+    log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms_step, wall))
+
+    # dominant kernel and its roofline
+    dom = max(rep.items(), key=lambda kv: kv[1]["ms"])
+    dname, d = dom
+    avg_ms = d["ms"] / d["launches"]
+    bytes_per_launch = d["bytes"] / d["launches"]
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    traffic = stored_traffic(dname)
+    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                   "avg_launch_ms": v["ms"] / v["launches"],
+                   "algorithmic_GBps": (v["bytes"] / v["launches"]) / (v["ms"] / v["launches"] / 1e3) / 1e9}
+               for k, v in sorted(rep.items(), key=lambda kv: -kv[1]["ms"])}
+    for k, v in kernels.items():
+        log("  %-40s %8.3f ms/step  %6.1f launches  %7.1f GB/s" % (k, v["ms_per_step"], v["launches_per_step"],
+                                                                  v["algorithmic_GBps"]))
+    # whole-step algorithmic bytes: the sum over kernels of their operands
+    step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
+
+    out = {
+        "metric": "screen+Fresnel grid points/sec (x lambda) at 1 MI355X; % HBM roofline; RMS err vs FP64",
+        "value": value,
+        "unit": "grid points*lambda/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Philox screens; no dataset exists for this method)",
+        "config": {"workload": "poly8192: 8 screens of 8192^2, 32 wavelengths 400-900 nm co-added, "
+                               "4 disk smears {0.5,1,2,4} R_F; R_F(650 nm)=90 px, R_diff(650 nm)=30 px, beta=11/3",
+                   "N": N, "n_real": n_real, "n_lambda": n_lam, "smear_radii_px": radii,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms},
+        "step_algorithmic_GB": step_bytes / 1e9,
+        "step_frac_of_hbm_roofline": (step_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
+        "kernels": kernels,
+    }
+
+    # ---------------------------------------------------------------- CPU baseline + accuracy
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        O.build()
+        sel = [0, n_lam // 2, n_lam - 1]
+        log("cpu baseline: oracle screen + %d of %d wavelengths at %d^2 (FP64)" % (len(sel), n_lam, N))
+        t0 = time.perf_counter()
+        phi_ref = O.screen(N, cfg.R_ref, cfg.beta, cfg.seed, 0)
+        I_refs = []
+        for j in sel:
+            rho = O.fresnel_radius_px(1.0, lams[j], cfg.z)
+            I_refs.append(O.propagate(phi_ref, rho, cfg.lam_ref / lams[j]))
+        cpu_s = time.perf_counter() - t0
+        cpu_units = float(N) * N * len(sel)
+        out["cpu_baseline"] = {"value": cpu_units / cpu_s, "unit": "grid points*lambda/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": "FP64 oracle: one 8192^2 screen + its propagation at 3 of the 32 "
+                                         "wavelengths (400, 658, 900 nm), %.1f s" % cpu_s}
+        # accuracy of the FP32 path against the FP64 oracle on the same sample
+        g_phi = phi[0:1].double().cpu().numpy()[0]
+        d = g_phi - phi_ref
+        acc = {"phi_rms_rel": float(np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(phi_ref * phi_ref)))}
+        erms, emax = [], []
+        for j, I_ref in zip(sel, I_refs):
+            Ig = scint.illumination_polychromatic(phi[0:1], 1.0, cfg.z, cfg.lam_ref, [lams[j]])
+            Ig = Ig.double().cpu().numpy()[0]
+            m = I_ref.mean()
+            diff = Ig - I_ref
+            erms.append(float(np.sqrt(np.mean(diff * diff)) / m))
+            emax.append(float(np.abs(diff).max() / m))
+        acc["I_rms_rel_max_over_lambda"] = max(erms)
+        acc["I_max_rel_max_over_lambda"] = max(emax)
+        acc["bar"] = {"rms": 2e-5, "max": 1e-3}
+        out["accuracy_vs_fp64_oracle"] = acc
+        log("accuracy: phi rms %.2e, I rms %.2e, I max %.2e" % (acc["phi_rms_rel"], max(erms), max(emax)))
+        del phi_ref, I_refs
+
+    # ---------------------------------------------------------------- secondary configurations
+    if not args.no_secondary:
+        sec = {}
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        # plain single-wavelength path, 32 calls, against the batched call (one screen)
+        one = phi[0:1]
+        acc_plain = torch.empty_like(one)
+        tmp = torch.empty_like(one)
+
+        def plain():
+            acc_plain.zero_()
+            for lam in lams:
+                scint.fresnel_propagate(one, 1.0, lam, cfg.z, cfg.lam_ref / lam, out=tmp)
+                acc_plain.add_(tmp, alpha=1.0 / n_lam)
+
+        batched_out = torch.empty_like(one)
+
+        def batched():
+            scint.illumination_polychromatic(one, 1.0, cfg.z, cfg.lam_ref, lams, out=batched_out)
+
+        t_plain = timed(plain, 2)
+        t_batched = timed(batched, 3)
+        diff = (acc_plain - batched_out).abs().max().item()
+        sec["batched_vs_plain_single_lambda"] = {"ms_plain_32_calls": t_plain, "ms_batched": t_batched,
+                                                  "speedup": t_plain / t_batched, "max_abs_diff": diff}
+        log("batched vs plain: %.2f ms vs %.2f ms (x%.2f)" % (t_batched, t_plain, t_plain / t_batched))
+        del acc_plain, tmp, batched_out
+
+        # single wavelength 4096^2, one screen+propagation per call, 12 calls
+        p4 = presets.SINGLE_4096
+        Iout = torch.empty((1, 4096, 4096), dtype=torch.float32, device=dev)
+
+        def single4096():
+            for c in p4:
+                for s in c.seeds:
+                    r = scint.load_library().ps_screen_fresnel(
+                        c.N, 1.0, c.R, c.beta, s, 0, 1, c.lam, c.z, 0, None,
+                        scint._ptr(Iout), scint._stream(dev))
+                    if r != 0:
+                        raise RuntimeError("ps_screen_fresnel failed %d" % r)
+
+        t4 = timed(single4096, 3)
+        sec["single_4096_screen_fresnel"] = {"ms_per_12_calls": t4, "pt_per_s": 12 * 4096.0 ** 2 / (t4 / 1e3)}
+        log("4096^2 single lambda: %.3f ms per call" % (t4 / 12))
+        del Iout
+
+        for c in presets.PAPER_SCALE:
+            if abs(c.beta - 11 / 3) > 1e-9:
+                continue
+            out_t = torch.empty((1, c.N, c.N), dtype=torch.float32, device=dev)
+
+            def paper():
+                r = scint.load_library().ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, 0, 1, c.lam, c.z, 0, None,
+                                                            scint._ptr(out_t), scint._stream(dev))
+                if r != 0:
+                    raise RuntimeError("ps_screen_fresnel failed %d" % r)
+
+            tp = timed(paper, 3)
+            sec["paper_%d_screen_fresnel" % c.N] = {"ms_per_call": tp, "pt_per_s": c.N ** 2 / (tp / 1e3)}
+            log("%d^2 single lambda: %.3f ms" % (c.N, tp))
+            del out_t
+
+        # forward + adjoint, 16 x 2048^2
+        g = presets.GRAD_2048
+        nr = presets.GRAD_N_REAL
+        It = torch.empty((nr, g.N, g.N), dtype=torch.float32, device=dev)
+        for i in range(nr):
+            It[i:i + 1] = scint.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, presets.GRAD_TARGET_SEED0 + i, g.lam, g.z)
+        gphi = torch.empty_like(It)
+        Igr = torch.empty_like(It)
+        phig = torch.empty_like(It)
+
+        def fwd_adj():
+            lib = scint.load_library()
+            st = scint._stream(dev)
+            r = lib.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, 1, 0, nr, g.lam, g.z, 0, scint._ptr(phig),
+                                      scint._ptr(Igr), st)
+            _, gI = scint.ps_l2_loss(Igr, It)
+            scint.fresnel_propagate_vjp(phig, 1.0, g.lam, g.z, gI, 1.0, out=gphi)
+            if r != 0:
+                raise RuntimeError("ps_screen_fresnel failed %d" % r)
+
+        tg = timed(fwd_adj, 3)
+        sec["grad_2048x16_forward_adjoint"] = {"ms_per_step": tg, "pt_per_s": nr * g.N ** 2 / (tg / 1e3)}
+        log("16 x 2048^2 forward+adjoint: %.3f ms" % tg)
+        out["secondary"] = sec
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

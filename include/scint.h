@@ -191,6 +191,23 @@ int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out,
 int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
                void *grad_out, double *loss_out, void *hip_stream);
 
+/*
+ * Kernel timing (instrumentation).  While enabled, every kernel the library
+ * launches is bracketed by two HIP events recorded on the stream it runs on,
+ * and per kernel name the library accumulates the event-measured duration,
+ * the launch count and the algorithmic bytes of each launch (the elements the
+ * kernel's operations must read and write, summed over its rows: complex
+ * elements count 2 reals; the 1-D chirp tables are not counted).
+ *   ps_timing_enable(1) clears the totals and starts recording; (0) stops.
+ *   ps_timing_count() waits for the recorded events and returns the number
+ *   of distinct kernel names; ps_timing_entry(i, ...) returns the i-th
+ *   (name copied into name_buf, NUL-terminated, at most buf_len bytes).
+ */
+int ps_timing_enable(int on);
+int ps_timing_count(void);
+int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches,
+                    double *bytes);
+
 /* Message for the last non-OK status of this thread ("" if none). */
 const char *ps_last_error(void);
 /* Message for the last warning of this thread ("" if none); cleared by every call. */

@@ -187,6 +187,77 @@ struct Carver {
     }
 };
 
+// ------------------------------------------------------------ timing
+// Optional per-kernel timing with events on the launch stream.
+struct PendingTiming {
+    std::string name;
+    hipEvent_t start, stop;
+    double bytes;
+};
+struct TimingTotal {
+    double ms = 0.0;
+    long long launches = 0;
+    double bytes = 0.0;
+};
+std::mutex g_timing_mutex;
+bool g_timing_on = false;
+std::vector<PendingTiming> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+std::map<std::string, TimingTotal> g_totals;
+
+hipEvent_t pool_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start event; returns false when timing is off.
+bool timing_begin(hipStream_t stream, hipEvent_t *start) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    if (!g_timing_on) return false;
+    *start = pool_event();
+    if (!*start) return false;
+    if (hipEventRecord(*start, stream) != hipSuccess) {
+        g_event_pool.push_back(*start);
+        return false;
+    }
+    return true;
+}
+
+void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, double bytes) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    hipEvent_t stop = pool_event();
+    if (!stop) return;
+    if (hipEventRecord(stop, stream) != hipSuccess) {
+        g_event_pool.push_back(stop);
+        return;
+    }
+    g_pending.push_back({name, start, stop, bytes});
+}
+
+void timing_drain() {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    for (auto &p : g_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.stop) == hipSuccess && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            auto &t = g_totals[p.name];
+            t.ms += ms;
+            t.launches += 1;
+            t.bytes += p.bytes;
+        }
+        g_event_pool.push_back(p.start);
+        g_event_pool.push_back(p.stop);
+    }
+    g_pending.clear();
+}
+
+const char *real_name(int dtype) { return dtype == PS_F64 ? "f64" : "f32"; }
+
 // ------------------------------------------------------------ row programs
 struct ProgBuilder {
     RowProgram p;
@@ -216,17 +287,68 @@ struct ProgBuilder {
     }
 };
 
-template <class Tag> int run_row(int dtype, int N, const RowProgram &p, hipStream_t stream) {
+// Algorithmic bytes of one row-pass launch: per element of a row, what each
+// operation reads or writes (ops inside the loop once per iteration).
+double row_bytes(const RowProgram &p, int n_ops, int dtype) {
+    const double rb = (double)real_bytes(dtype);
+    double per = 0.0;
+    bool in_loop = false;
+    for (int i = 0; i < n_ops; ++i) {
+        const RowOp &o = p.op[i];
+        double b = 0.0;
+        switch (o.code) {
+        case ROP_LOOP: in_loop = true; break;
+        case ROP_ENDLOOP: in_loop = false; break;
+        case ROP_LOAD_C: case ROP_STORE_C: b = 2 * rb; break;
+        case ROP_LOAD_R: case ROP_LOAD_PHASE: case ROP_KEEP_R: case ROP_MUL_RLOAD: case ROP_MUL_RTAB2D:
+        case ROP_GRAD_PHI: case ROP_DOT_R: b = rb; break;
+        case ROP_STORE_R: b = o.ptr ? rb : 0.0; break;
+        case ROP_STORE_ACC: b = (o.flags & RF_ADD) ? 2 * rb : rb; break;
+        default: break;
+        }
+        per += in_loop ? b * p.n_iter : b;
+    }
+    return per * (double)p.N * (double)p.total_rows;
+}
+
+template <class Tag> const char *prog_name();
+#define SCINT_PROG_NAME(P) \
+    template <> const char *prog_name<P##Tag>() { return #P; }
+SCINT_PROG_NAME(ProgNoise)
+SCINT_PROG_NAME(ProgScreen)
+SCINT_PROG_NAME(ProgScreenProp)
+SCINT_PROG_NAME(ProgPhaseProp)
+SCINT_PROG_NAME(ProgPropIntensity)
+SCINT_PROG_NAME(ProgRealFwd)
+SCINT_PROG_NAME(ProgFwdRe)
+SCINT_PROG_NAME(ProgSmearMid)
+SCINT_PROG_NAME(ProgInvRe)
+SCINT_PROG_NAME(ProgVjpY)
+SCINT_PROG_NAME(ProgVjpX)
+#undef SCINT_PROG_NAME
+
+template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_ops, hipStream_t stream) {
     const void *tw = nullptr;
     if (int rc = get_twiddles(N, dtype, &tw)) return rc;
+    hipEvent_t t0 = nullptr;
+    const bool timed = timing_begin(stream, &t0);
     hipError_t e = dtype == PS_F64 ? launch_row<double, Tag>(N, p, tw, stream)
                                    : launch_row<float, Tag>(N, p, tw, stream);
     if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("row pass launch: ") + hipGetErrorString(e));
+    if (timed)
+        timing_end(stream, t0,
+                   std::string("row_") + prog_name<Tag>() + "_" + real_name(dtype) + "_N" + std::to_string(N),
+                   row_bytes(p, n_ops, dtype));
     return PS_OK;
 }
 
 int transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes, hipStream_t stream) {
+    hipEvent_t t0 = nullptr;
+    const bool timed = timing_begin(stream, &t0);
     HIP_TRY(launch_transpose(in, out, N, nbatch, elem_bytes, stream));
+    if (timed)
+        timing_end(stream, t0, "transpose_" + std::to_string(elem_bytes) + "B_N" + std::to_string(N),
+                   2.0 * elem_bytes * (double)N * N * (double)nbatch);
     return PS_OK;
 }
 
@@ -274,7 +396,7 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
     ProgBuilder a(N, (int64_t)nb * N);
     set_noise(a.p, N, R, beta, seed, r0);
     a.op(ROP_NOISE).op(ROP_FFT_INV).op(ROP_STORE_C, W1, nn(N), N);
-    if (int rc = run_row<ProgNoiseTag>(dtype, N, a.p, stream)) return rc;
+    if (int rc = run_row<ProgNoiseTag>(dtype, N, a.p, a.n, stream)) return rc;
     return transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream);
 }
 
@@ -284,6 +406,35 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
 extern "C" {
 
 int ps_version(void) { return 10000; }
+
+int ps_timing_enable(int on) {
+    timing_drain();
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    if (on) g_totals.clear();
+    g_timing_on = on != 0;
+    return PS_OK;
+}
+
+int ps_timing_count(void) {
+    timing_drain();
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    return (int)g_totals.size();
+}
+
+int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches, double *bytes) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    if (i < 0 || i >= (int)g_totals.size()) return fail(PS_E_SIZE, "timing entry index out of range");
+    auto it = g_totals.begin();
+    std::advance(it, i);
+    if (name_buf && buf_len > 0) {
+        std::strncpy(name_buf, it->first.c_str(), (size_t)buf_len - 1);
+        name_buf[buf_len - 1] = '\0';
+    }
+    if (total_ms) *total_ms = it->second.ms;
+    if (launches) *launches = it->second.launches;
+    if (bytes) *bytes = it->second.bytes;
+    return PS_OK;
+}
 
 const char *ps_last_error(void) { return g_last_error.c_str(); }
 const char *ps_last_warning(void) { return g_last_warning.c_str(); }
@@ -348,7 +499,7 @@ int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed, 
         ProgBuilder b(N, (int64_t)nb * N);
         char *phi = static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
         b.op(ROP_LOAD_C, W2, nn(N), N).op(ROP_FFT_INV).op(ROP_SQRT2RE).op(ROP_STORE_R, phi, nn(N), N, 0, 0, 1.0);
-        if (int rc = run_row<ProgScreenTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = run_row<ProgScreenTag>(dtype, N, b.p, b.n, stream)) return rc;
     }
     return PS_OK;
 }
@@ -394,7 +545,7 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
             .op(ROP_MUL_TAB, H)
             .op(ROP_FFT_INV)
             .op(ROP_STORE_C, W1, nn(N), N);
-        if (int rc = run_row<ProgScreenPropTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = run_row<ProgScreenPropTag>(dtype, N, b.p, b.n, stream)) return rc;
         if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
         ProgBuilder d(N, (int64_t)nb * N);
         d.op(ROP_LOOP)
@@ -405,7 +556,7 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
             .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0)
             .op(ROP_ENDLOOP)
             .op(ROP_STORE_ACC, W1, nn(N), N);
-        if (int rc = run_row<ProgPropIntensityTag>(dtype, N, d.p, stream)) return rc;
+        if (int rc = run_row<ProgPropIntensityTag>(dtype, N, d.p, d.n, stream)) return rc;
         char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
         if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
     }
@@ -431,7 +582,7 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
         .op(ROP_FFT_INV)
         .op(ROP_STORE_C, W1, nn(N), N, (int64_t)nb * nn(N))
         .op(ROP_ENDLOOP);
-    if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, stream)) return rc;
+    if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, a.n, stream)) return rc;
     if (int rc = transpose(W1, W2, N, (int64_t)nb * C, 2 * (int)real_bytes(dtype), stream)) return rc;
     ProgBuilder b(N, (int64_t)nb * N);
     b.p.n_iter = C;
@@ -444,7 +595,7 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
         .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, RF_ITER_WEIGHT)
         .op(ROP_ENDLOOP)
         .op(ROP_STORE_ACC, Iacc, nn(N), N, 0, add ? RF_ADD : 0);
-    return run_row<ProgPropIntensityTag>(dtype, N, b.p, stream);
+    return run_row<ProgPropIntensityTag>(dtype, N, b.p, b.n, stream);
 }
 
 int fresnel_propagate(int N, double delta, double lambda, double z, const void *phi, double phase_scale, int n,
@@ -587,13 +738,13 @@ static int get_disk_spectrum(int N, double Rpx, int dtype, hipStream_t stream, c
     if (!rc) {
         ProgBuilder a(N, N);
         a.op(ROP_LOAD_R, tab, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, 0, N);
-        rc = run_row<ProgRealFwdTag>(dtype, N, a.p, stream);
+        rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream);
     }
     if (!rc) rc = transpose(W1, W2, N, 1, 2 * (int)real_bytes(dtype), stream);
     if (!rc) {
         ProgBuilder b(N, N);
         b.op(ROP_LOAD_C, W2, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_R, tab, 0, N, 0, 0, 1.0 / (double)nn(N));
-        rc = run_row<ProgFwdReTag>(dtype, N, b.p, stream);
+        rc = run_row<ProgFwdReTag>(dtype, N, b.p, b.n, stream);
     }
     if (!rc) {
         e = hipStreamSynchronize(stream);
@@ -649,7 +800,7 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
         const char *Iin = static_cast<const char *>(I_in) + (size_t)b0 * rb1;
         ProgBuilder a(N, (int64_t)nb * N);
         a.op(ROP_LOAD_R, Iin, nn(N), N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, nn(N), N);
-        if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, stream)) return rc;
+        if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream)) return rc;
         if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
         ProgBuilder b(N, (int64_t)nb * N);
         b.p.n_iter = n_r;
@@ -662,12 +813,12 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
             .op(ROP_FFT_INV)
             .op(ROP_STORE_C, V1, (int64_t)n_r * nn(N), N, nn(N))
             .op(ROP_ENDLOOP);
-        if (int rc = run_row<ProgSmearMidTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = run_row<ProgSmearMidTag>(dtype, N, b.p, b.n, stream)) return rc;
         if (int rc = transpose(V1, V2, N, (int64_t)nb * n_r, (int)(cbytes / nn(N)), stream)) return rc;
         ProgBuilder d(N, (int64_t)nb * n_r * N);
         char *Iout = static_cast<char *>(I_out) + (size_t)b0 * n_r * rb1;
         d.op(ROP_LOAD_C, V2, nn(N), N).op(ROP_FFT_INV).op(ROP_STORE_R, Iout, nn(N), N, 0, 0, 1.0);
-        if (int rc = run_row<ProgInvReTag>(dtype, N, d.p, stream)) return rc;
+        if (int rc = run_row<ProgInvReTag>(dtype, N, d.p, d.n, stream)) return rc;
     }
     return PS_OK;
 }
@@ -720,7 +871,7 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
             .op(ROP_FFT_INV)
             .op(ROP_STORE_C, W1, nn(N), N)
             .op(ROP_ENDLOOP);
-        if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, stream)) return rc;
+        if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, a.n, stream)) return rc;
         if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
         if (int rc = transpose(gI, Gt, N, nb, (int)real_bytes(dtype), stream)) return rc;
         // y-propagation to A (transposed), g_A = 2 grad_I A, adjoint y-propagation
@@ -734,7 +885,7 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
             .op(ROP_MUL_TAB, H, 0, 0, 0, RF_CONJ)
             .op(ROP_FFT_INV)
             .op(ROP_STORE_C, W1, nn(N), N);
-        if (int rc = run_row<ProgVjpYTag>(dtype, N, b.p, stream)) return rc;
+        if (int rc = run_row<ProgVjpYTag>(dtype, N, b.p, b.n, stream)) return rc;
         if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
         // adjoint x-propagation, dL/dphi = s Im(g_U conj U), and sum phi dL/dphi per row
         char *gphi = static_cast<char *>(grad_phi_out) + (size_t)b0 * rb1;
@@ -746,7 +897,7 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
             .op(ROP_GRAD_PHI, ph, nn(N), N, 0, 0, phase_scale)
             .op(ROP_STORE_R, gphi, nn(N), N, 0, 0, 1.0)
             .op(ROP_DOT_R, ph, nn(N), N, 0, 0, 0.0, rowdot);
-        if (int rc = run_row<ProgVjpXTag>(dtype, N, d.p, stream)) return rc;
+        if (int rc = run_row<ProgVjpXTag>(dtype, N, d.p, d.n, stream)) return rc;
         if (phi_dot_grad_out) {
             HIP_TRY(launch_finalize_sums(rowdot, N, nb, 1.0, bdot, stream));
             HIP_TRY(hipMemcpyAsync(dots.data() + b0, bdot, (size_t)nb * 8, hipMemcpyDeviceToHost, stream));

@@ -46,6 +46,9 @@ SIGNATURES = {
     "ps_last_warning": (ctypes.c_char_p, []),
     "ps_release_cache": (_c_int, []),
     "ps_version": (_c_int, []),
+    "ps_timing_enable": (_c_int, [_c_int]),
+    "ps_timing_count": (_c_int, []),
+    "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp]),
 }
 
 _lock = threading.Lock()
@@ -139,6 +142,24 @@ def release_cache() -> None:
 
 def version() -> int:
     return load_library().ps_version()
+
+
+def timing_enable(on: bool = True) -> None:
+    """Start (clearing totals) or stop per-kernel event timing in the library."""
+    _check("ps_timing_enable", load_library().ps_timing_enable(1 if on else 0))
+
+
+def timing_report() -> dict:
+    """{kernel name: {"ms": total, "launches": n, "bytes": algorithmic bytes}}
+    for the kernels launched while timing was enabled (waits for them)."""
+    lib = load_library()
+    out = {}
+    for i in range(lib.ps_timing_count()):
+        buf = ctypes.create_string_buffer(256)
+        ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        _check("ps_timing_entry", lib.ps_timing_entry(i, buf, 256, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        out[buf.value.decode()] = {"ms": ms.value, "launches": n.value, "bytes": b.value}
+    return out
 
 
 # ------------------------------------------------------------------ entry points
