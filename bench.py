@@ -23,7 +23,8 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed FMA)
 
 
 def log(*a):
@@ -67,6 +68,9 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--calib-copy-gb", type=float, default=0.0,
+                    help="first copy this many GB device-to-device with one plain copy kernel, as the "
+                         "reference of known size for the FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures the single-GPU path only (one MI355X); --gpus %d is not supported" % args.gpus,
@@ -85,6 +89,16 @@ def main(argv=None) -> int:
         return 1
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.calib_copy_gb > 0:
+        n = int(args.calib_copy_gb * 1e9) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (4 * n, 4 * n))
+        del src, dst
 
     cfg = presets.POLY_8192
     N, n_real, lams, radii = cfg.N, cfg.n_real, cfg.lambdas, cfg.smear_radii
@@ -122,20 +136,35 @@ def main(argv=None) -> int:
     value = units / (ms_step / 1e3)
     log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms_step, wall))
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline.  Row passes that run FFTs are bound by
+    # VALU issue (their HBM traffic is a fraction of the bandwidth); the
+    # transposes and other FFT-free kernels are bound by HBM.
     dom = max(rep.items(), key=lambda kv: kv[1]["ms"])
     dname, d = dom
     avg_ms = d["ms"] / d["launches"]
     bytes_per_launch = d["bytes"] / d["launches"]
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    flops_per_launch = d["flops"] / d["launches"]
+    gbps = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    tflops = flops_per_launch / (avg_ms / 1e3) / 1e12
     traffic = stored_traffic(dname)
     kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                    "avg_launch_ms": v["ms"] / v["launches"],
-                   "algorithmic_GBps": (v["bytes"] / v["launches"]) / (v["ms"] / v["launches"] / 1e3) / 1e9}
+                   "algorithmic_GBps": (v["bytes"] / v["launches"]) / (v["ms"] / v["launches"] / 1e3) / 1e9,
+                   "algorithmic_TFLOPs": (v["flops"] / v["launches"]) / (v["ms"] / v["launches"] / 1e3) / 1e12}
                for k, v in sorted(rep.items(), key=lambda kv: -kv[1]["ms"])}
     for k, v in kernels.items():
-        log("  %-40s %8.3f ms/step  %6.1f launches  %7.1f GB/s" % (k, v["ms_per_step"], v["launches_per_step"],
-                                                                  v["algorithmic_GBps"]))
+        log("  %-40s %8.3f ms/step  %6.1f launches  %7.1f GB/s  %6.2f TFLOP/s" % (
+            k, v["ms_per_step"], v["launches_per_step"], v["algorithmic_GBps"], v["algorithmic_TFLOPs"]))
+    if flops_per_launch > 0:
+        roofline = {"bound": "alu", "kernel": dname, "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                    "algorithmic_flops_per_launch": flops_per_launch,
+                    "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
+                    "hbm_achieved_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBS}
+    else:
+        roofline = {"bound": "hbm", "kernel": dname, "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbps / HBM_PEAK_GBS, "traffic": traffic,
+                    "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms}
     # whole-step algorithmic bytes: the sum over kernels of their operands
     step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
 
@@ -156,9 +185,7 @@ def main(argv=None) -> int:
                                "4 disk smears {0.5,1,2,4} R_F; R_F(650 nm)=90 px, R_diff(650 nm)=30 px, beta=11/3",
                    "N": N, "n_real": n_real, "n_lambda": n_lam, "smear_radii_px": radii,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms},
+        "roofline": roofline,
         "step_algorithmic_GB": step_bytes / 1e9,
         "step_frac_of_hbm_roofline": (step_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
         "kernels": kernels,

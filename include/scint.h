@@ -11,8 +11,9 @@
  *  - Grids are square, N x N pixels of side `delta` (Sect. 3.1).  Supported N
  *    are listed by ps_supported_size(); every other N returns PS_E_SIZE.
  *  - Arrays are device memory owned by the caller, contiguous, row-major
- *    [batch][N][N] with y (row) slow and x fast.  Real arrays hold float
- *    (dtype PS_F32) or double (PS_F64).  The library never frees caller memory.
+ *    [batch][N][N] with y (row) slow and x fast, 16-byte aligned (else
+ *    PS_E_PARAM).  Real arrays hold float (dtype PS_F32) or double (PS_F64).
+ *    The library never frees caller memory.
  *  - delta, lambda, z, r_diff and source radii share one length unit of the
  *    caller's choice.  The Fresnel radius is R_F = sqrt(lambda z / 2 pi)
  *    (Sect. 2, Eq. Rfresnel); the screen-observer distance z is the effective
@@ -195,9 +196,12 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
  * Kernel timing (instrumentation).  While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the stream it runs on,
  * and per kernel name the library accumulates the event-measured duration,
- * the launch count and the algorithmic bytes of each launch (the elements the
+ * the launch count, the algorithmic bytes of each launch (the elements the
  * kernel's operations must read and write, summed over its rows: complex
- * elements count 2 reals; the 1-D chirp tables are not counted).
+ * elements count 2 reals; the 1-D chirp tables are not counted) and its
+ * algorithmic floating-point operations (5 N log2 N per length-N complex DFT,
+ * 6 per complex multiply, 2 per real-by-complex multiply, 5 per weighted
+ * |A|^2 accumulation; sine, cosine and the noise generator not counted).
  *   ps_timing_enable(1) clears the totals and starts recording; (0) stops.
  *   ps_timing_count() waits for the recorded events and returns the number
  *   of distinct kernel names; ps_timing_entry(i, ...) returns the i-th
@@ -206,7 +210,7 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
 int ps_timing_enable(int on);
 int ps_timing_count(void);
 int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches,
-                    double *bytes);
+                    double *bytes, double *flops);
 
 /* Message for the last non-OK status of this thread ("" if none). */
 const char *ps_last_error(void);

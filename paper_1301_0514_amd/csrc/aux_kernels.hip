@@ -9,8 +9,48 @@
 namespace scint {
 
 // ---------------------------------------------------------------- transpose
-// TILE x TILE tile through LDS (one padding column), 256 threads; each
-// thread moves TILE*TILE/256 elements.  Reads and writes are row-contiguous.
+// 64 x 64 tile through LDS, 256 threads.  Each lane moves two adjacent
+// elements at once (16-byte accesses for complex64, 8 for float), 32 lanes
+// per 64-element row, so both the row reads and the transposed row writes
+// are 512-byte contiguous runs.  N is even (every supported size is), so an
+// element pair never straddles the edge of a ragged tile.
+template <typename T> struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_pair_kernel(const T *__restrict__ in, T *__restrict__ out, int N) {
+    __shared__ T tile[64][64 + 2];
+    const int lx = threadIdx.x % 32, ly = threadIdx.x / 32;  // 32 pair-lanes x 8 rows
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 64;
+    const int64_t base = (int64_t)blockIdx.z * N * N;
+    const T *src = in + base;
+    T *dst = out + base;
+    const int xa = x0 + 2 * lx;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = ly + 8 * i, y = y0 + r;
+        if (y < N && xa < N) {
+            const Pair<T> v = *reinterpret_cast<const Pair<T> *>(src + (int64_t)y * N + xa);
+            tile[r][2 * lx] = v.a;
+            tile[r][2 * lx + 1] = v.b;
+        }
+    }
+    __syncthreads();
+    const int ya = y0 + 2 * lx;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = ly + 8 * i, x = x0 + r;
+        if (x < N && ya < N) {
+            Pair<T> v;
+            v.a = tile[2 * lx][r];
+            v.b = tile[2 * lx + 1][r];
+            *reinterpret_cast<Pair<T> *>(dst + (int64_t)x * N + ya) = v;
+        }
+    }
+}
+
+// complex128: one 16-byte element per lane, TILE x TILE tile.
 template <typename T, int TILE>
 __global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ in, T *__restrict__ out, int N) {
     __shared__ T tile[TILE][TILE + 1];
@@ -33,25 +73,26 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ in
     }
 }
 
+struct alignas(8) Elem8 {
+    float a, b;
+};
 struct alignas(16) Elem16 {
     double a, b;
 };
 
 hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes,
                             hipStream_t stream) {
+    if (N % 2 != 0) return hipErrorInvalidValue;
     for (int64_t b0 = 0; b0 < nbatch; b0 += 65535) {
         const int nb = (int)((nbatch - b0) < 65535 ? (nbatch - b0) : 65535);
         const int64_t off = b0 * (int64_t)N * N;
+        const dim3 grid64((N + 63) / 64, (N + 63) / 64, nb);
         if (elem_bytes == 4) {
-            constexpr int TILE = 64;
-            dim3 grid((N + TILE - 1) / TILE, (N + TILE - 1) / TILE, nb);
-            hipLaunchKernelGGL((transpose_kernel<float, TILE>), grid, dim3(256), 0, stream,
+            hipLaunchKernelGGL((transpose_pair_kernel<float>), grid64, dim3(256), 0, stream,
                                static_cast<const float *>(in) + off, static_cast<float *>(out) + off, N);
         } else if (elem_bytes == 8) {
-            constexpr int TILE = 64;
-            dim3 grid((N + TILE - 1) / TILE, (N + TILE - 1) / TILE, nb);
-            hipLaunchKernelGGL((transpose_kernel<double, TILE>), grid, dim3(256), 0, stream,
-                               static_cast<const double *>(in) + off, static_cast<double *>(out) + off, N);
+            hipLaunchKernelGGL((transpose_pair_kernel<Elem8>), grid64, dim3(256), 0, stream,
+                               static_cast<const Elem8 *>(in) + off, static_cast<Elem8 *>(out) + off, N);
         } else if (elem_bytes == 16) {
             constexpr int TILE = 32;
             dim3 grid((N + TILE - 1) / TILE, (N + TILE - 1) / TILE, nb);

@@ -113,8 +113,12 @@ template <int R, int S> struct RootTable {
 // Base radices 2, 4, 5; larger radices by one Cooley-Tukey split R = R1 R2
 // (decimation in time) with compile-time twiddles.
 // ---------------------------------------------------------------------------
+#ifndef SCINT_SPLIT32
+#define SCINT_SPLIT32 4
+#endif
 template <int R> constexpr int split_factor() {
-    if constexpr (R % 4 == 0 && R != 8) return 4;
+    if constexpr (R == 32) return SCINT_SPLIT32;
+    else if constexpr (R % 4 == 0 && R != 8) return 4;
     else if constexpr (R % 2 == 0) return 2;
     else return 5;
 }

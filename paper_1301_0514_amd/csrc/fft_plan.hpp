@@ -17,6 +17,15 @@ namespace scint {
 
 template <int L> struct Plan;  // only the sizes below exist
 
+constexpr bool plan_ok(int L, int E, const int *R, int ns) {
+    int prod = 1;
+    for (int s = 0; s < ns; ++s) {
+        if (R[s] < 2 || E % R[s] != 0) return false;
+        prod *= R[s];
+    }
+    return prod == L && L % E == 0 && L / E <= 1024;
+}
+
 #define SCINT_PLAN(L_, E_, ...)                                                 \
     template <> struct Plan<L_> {                                               \
         static constexpr int L = L_;                                            \
@@ -24,7 +33,12 @@ template <int L> struct Plan;  // only the sizes below exist
         static constexpr int R[] = {__VA_ARGS__};                               \
         static constexpr int NS = sizeof(R) / sizeof(int);                      \
         static constexpr int T = L_ / E_;                                       \
+        static_assert(plan_ok(L_, E_, R, NS),                                   \
+                      "radices must multiply to L and each divide E");          \
     };
+
+// expands a size list given through another macro
+#define SCINT_PLAN_EXPAND(...) SCINT_PLAN(__VA_ARGS__)
 
 // powers of two
 SCINT_PLAN(16, 16, 16)
@@ -34,10 +48,22 @@ SCINT_PLAN(128, 16, 16, 8)
 SCINT_PLAN(256, 16, 16, 16)
 SCINT_PLAN(512, 8, 8, 8, 8)
 SCINT_PLAN(1024, 16, 16, 16, 4)
-SCINT_PLAN(2048, 16, 16, 16, 8)
-SCINT_PLAN(4096, 16, 16, 16, 16)
-SCINT_PLAN(8192, 16, 16, 16, 16, 2)
-SCINT_PLAN(16384, 32, 16, 16, 16, 4)
+#ifndef SCINT_PLAN_2048
+#define SCINT_PLAN_2048 16, 16, 16, 8
+#endif
+SCINT_PLAN_EXPAND(2048, SCINT_PLAN_2048)
+#ifndef SCINT_PLAN_4096
+#define SCINT_PLAN_4096 32, 32, 8, 16
+#endif
+SCINT_PLAN_EXPAND(4096, SCINT_PLAN_4096)
+#ifndef SCINT_PLAN_8192
+#define SCINT_PLAN_8192 32, 32, 32, 8
+#endif
+SCINT_PLAN_EXPAND(8192, SCINT_PLAN_8192)
+#ifndef SCINT_PLAN_16384
+#define SCINT_PLAN_16384 32, 32, 32, 16
+#endif
+SCINT_PLAN_EXPAND(16384, SCINT_PLAN_16384)
 // 2^a 5^b
 SCINT_PLAN(40, 20, 4, 10)
 SCINT_PLAN(80, 20, 4, 20)
@@ -54,8 +80,12 @@ SCINT_PLAN(2560, 20, 4, 4, 4, 4, 10)
 SCINT_PLAN(4000, 20, 20, 20, 10)
 SCINT_PLAN(5000, 10, 10, 10, 10, 5)
 SCINT_PLAN(8000, 20, 20, 20, 20)
-SCINT_PLAN(10000, 10, 10, 10, 10, 10)
+#ifndef SCINT_PLAN_10000
+#define SCINT_PLAN_10000 10, 10, 10, 10, 10
+#endif
+SCINT_PLAN_EXPAND(10000, SCINT_PLAN_10000)
 
+#undef SCINT_PLAN_EXPAND
 #undef SCINT_PLAN
 
 // Sizes in ascending order, per precision (FP64 stops at 8192 because a

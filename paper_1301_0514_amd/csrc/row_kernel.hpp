@@ -11,13 +11,16 @@ namespace scint {
 
 // LDS layout of a row: one padding slot every 16 elements breaks the
 // power-of-two strides of the Stockham writes across banks.
-constexpr int kLdsPadShift = 4;
-__device__ __forceinline__ int lds_index(int p) { return p + (p >> kLdsPadShift); }
+#ifndef SCINT_LDS_PAD_SHIFT
+#define SCINT_LDS_PAD_SHIFT 5
+#endif
+constexpr int kLdsPadShift = SCINT_LDS_PAD_SHIFT;
+__device__ __forceinline__ int lds_index(int p) { return kLdsPadShift > 0 ? p + (p >> kLdsPadShift) : p; }
 
 template <typename Real, int L> struct RowCfg {
     using P = Plan<L>;
     static constexpr int T = P::T;
-    static constexpr int LDS_STRIDE = L + (L >> kLdsPadShift);
+    static constexpr int LDS_STRIDE = kLdsPadShift > 0 ? L + (L >> kLdsPadShift) : L;
     static constexpr int ELEM = 2 * (int)sizeof(Real);
     static constexpr int B_THREADS = T >= 256 ? 1 : 256 / T;
     static constexpr int B_LDS = (P::NS > 1) ? ((65536 / (LDS_STRIDE * ELEM)) > 0 ? 65536 / (LDS_STRIDE * ELEM) : 1)
@@ -32,7 +35,10 @@ template <typename Real, int L> struct RowCfg {
     // lower bound on the occupancy the register allocator must keep: two
     // waves per SIMD (up to 256 VGPRs), which the heaviest programs need
     // without spilling; lighter programs use fewer registers anyway
-    static constexpr int WAVES_PER_EU = 2;
+#ifndef SCINT_WAVES_PER_EU
+#define SCINT_WAVES_PER_EU 2
+#endif
+    static constexpr int WAVES_PER_EU = SCINT_WAVES_PER_EU;
 };
 
 // ---------------------------------------------------------------- FFT
@@ -90,9 +96,19 @@ __device__ __forceinline__ void fft_forward(cpx<Real> (&v)[Plan<L>::E], cpx<Real
 template <typename Real> __device__ __forceinline__ cpx<Real> expi_turns(double turns);
 template <> __device__ __forceinline__ cpx<float> expi_turns<float>(double turns) {
     const double f = turns - rint(turns);
+#ifndef SCINT_FAST_SINCOS
+#define SCINT_FAST_SINCOS 1
+#endif
+#if SCINT_FAST_SINCOS
+    // hardware sine/cosine of 2 pi x (x in turns, |x| <= 1/2; absolute error
+    // about 1.2e-7 measured on gfx950, the same order as FP32 rounding)
+    const float x = (float)f;
+    return {__builtin_amdgcn_cosf(x), __builtin_amdgcn_sinf(x)};
+#else
     float s, c;
     sincospif((float)(2.0 * f), &s, &c);
     return {c, s};
+#endif
 }
 template <> __device__ __forceinline__ cpx<double> expi_turns<double>(double turns) {
     const double f = turns - rint(turns);
@@ -364,8 +380,10 @@ using ProgNoise = OpList<ROP_NOISE, ROP_FFT_INV, ROP_STORE_C>;
 using ProgScreen = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R>;
 using ProgScreenProp = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R, ROP_EXP_RE, ROP_FFT_FWD,
                               ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
-using ProgPhaseProp = OpList<ROP_KEEP_R, ROP_LOOP, ROP_EXP_KEEP, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV,
-                             ROP_STORE_C, ROP_ENDLOOP>;
+// (the phase is re-read for every wavelength: keeping it in registers
+// costs more in occupancy than the cached re-read)
+using ProgPhaseProp = OpList<ROP_LOOP, ROP_LOAD_PHASE, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C,
+                             ROP_ENDLOOP>;
 using ProgPropIntensity = OpList<ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_ACC_ABS2,
                                  ROP_ENDLOOP, ROP_STORE_ACC>;
 using ProgRealFwd = OpList<ROP_LOAD_R, ROP_FFT_FWD, ROP_STORE_C>;

@@ -95,6 +95,15 @@ int check_common(int N, int dtype, int n) {
 
 size_t real_bytes(int dtype) { return dtype == PS_F64 ? 8 : 4; }
 
+// Device arrays must be 16-byte aligned (the kernels use 8- and 16-byte
+// vector accesses).  NULL passes (optional arrays are checked separately).
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+int check_aligned(std::initializer_list<const void *> ptrs) {
+    for (const void *p : ptrs)
+        if (p && !aligned16(p)) return fail(PS_E_PARAM, "device arrays must be 16-byte aligned");
+    return PS_OK;
+}
+
 // true if [a, a+na) and [b, b+nb) overlap
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
@@ -192,12 +201,13 @@ struct Carver {
 struct PendingTiming {
     std::string name;
     hipEvent_t start, stop;
-    double bytes;
+    double bytes, flops;
 };
 struct TimingTotal {
     double ms = 0.0;
     long long launches = 0;
     double bytes = 0.0;
+    double flops = 0.0;
 };
 std::mutex g_timing_mutex;
 bool g_timing_on = false;
@@ -229,7 +239,7 @@ bool timing_begin(hipStream_t stream, hipEvent_t *start) {
     return true;
 }
 
-void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, double bytes) {
+void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, double bytes, double flops) {
     std::lock_guard<std::mutex> lock(g_timing_mutex);
     hipEvent_t stop = pool_event();
     if (!stop) return;
@@ -237,7 +247,7 @@ void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, d
         g_event_pool.push_back(stop);
         return;
     }
-    g_pending.push_back({name, start, stop, bytes});
+    g_pending.push_back({name, start, stop, bytes, flops});
 }
 
 void timing_drain() {
@@ -249,6 +259,7 @@ void timing_drain() {
             t.ms += ms;
             t.launches += 1;
             t.bytes += p.bytes;
+            t.flops += p.flops;
         }
         g_event_pool.push_back(p.start);
         g_event_pool.push_back(p.stop);
@@ -311,6 +322,32 @@ double row_bytes(const RowProgram &p, int n_ops, int dtype) {
     return per * (double)p.N * (double)p.total_rows;
 }
 
+// Algorithmic floating-point operations of one row-pass launch: 5 N log2 N
+// per length-N complex DFT (the usual count), 6 per complex multiply, 2 per
+// real-by-complex multiply, 5 for w |v|^2 accumulated; sine/cosine and the
+// noise generator are not counted.
+double row_flops(const RowProgram &p, int n_ops) {
+    const double log2n = std::log2((double)p.N);
+    double per = 0.0;
+    bool in_loop = false;
+    for (int i = 0; i < n_ops; ++i) {
+        double f = 0.0;
+        switch (p.op[i].code) {
+        case ROP_LOOP: in_loop = true; break;
+        case ROP_ENDLOOP: in_loop = false; break;
+        case ROP_FFT_FWD: case ROP_FFT_INV: f = 5.0 * log2n; break;
+        case ROP_MUL_TAB: f = 6.0; break;
+        case ROP_MUL_RTAB2D: case ROP_MUL_RLOAD: case ROP_DOT_R: f = 2.0; break;
+        case ROP_ACC_ABS2: f = 5.0; break;
+        case ROP_GRAD_PHI: f = 4.0; break;
+        case ROP_SQRT2RE: f = 1.0; break;
+        default: break;
+        }
+        per += in_loop ? f * p.n_iter : f;
+    }
+    return per * (double)p.N * (double)p.total_rows;
+}
+
 template <class Tag> const char *prog_name();
 #define SCINT_PROG_NAME(P) \
     template <> const char *prog_name<P##Tag>() { return #P; }
@@ -338,7 +375,7 @@ template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_op
     if (timed)
         timing_end(stream, t0,
                    std::string("row_") + prog_name<Tag>() + "_" + real_name(dtype) + "_N" + std::to_string(N),
-                   row_bytes(p, n_ops, dtype));
+                   row_bytes(p, n_ops, dtype), row_flops(p, n_ops));
     return PS_OK;
 }
 
@@ -348,7 +385,7 @@ int transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes, 
     HIP_TRY(launch_transpose(in, out, N, nbatch, elem_bytes, stream));
     if (timed)
         timing_end(stream, t0, "transpose_" + std::to_string(elem_bytes) + "B_N" + std::to_string(N),
-                   2.0 * elem_bytes * (double)N * N * (double)nbatch);
+                   2.0 * elem_bytes * (double)N * N * (double)nbatch, 0.0);
     return PS_OK;
 }
 
@@ -421,7 +458,8 @@ int ps_timing_count(void) {
     return (int)g_totals.size();
 }
 
-int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches, double *bytes) {
+int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches, double *bytes,
+                    double *flops) {
     std::lock_guard<std::mutex> lock(g_timing_mutex);
     if (i < 0 || i >= (int)g_totals.size()) return fail(PS_E_SIZE, "timing entry index out of range");
     auto it = g_totals.begin();
@@ -433,6 +471,7 @@ int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long l
     if (total_ms) *total_ms = it->second.ms;
     if (launches) *launches = it->second.launches;
     if (bytes) *bytes = it->second.bytes;
+    if (flops) *flops = it->second.flops;
     return PS_OK;
 }
 
@@ -479,6 +518,7 @@ int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed, 
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n_real)) return rc;
     if (!phi_out) return fail(PS_E_NULL, "phi_out is NULL");
+    if (int rc = check_aligned({phi_out})) return rc;
     if (!finite_pos(delta) || !finite_pos(r_diff)) return fail(PS_E_PARAM, "delta and r_diff must be finite and > 0");
     if (!(std::isfinite(beta) && beta > 2.0 && beta < 4.0)) return fail(PS_E_PARAM, "beta must lie in (2, 4)");
     if (delta >= r_diff / 2.0) g_last_warning = "pixel side >= R_diff/2: the phase variations are undersampled";
@@ -510,6 +550,7 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n_real)) return rc;
     if (!I_out) return fail(PS_E_NULL, "I_out is NULL");
+    if (int rc = check_aligned({I_out, phi_out})) return rc;
     if (!finite_pos(delta) || !finite_pos(r_diff) || !finite_pos(lambda) || !finite_pos(z))
         return fail(PS_E_PARAM, "delta, r_diff, lambda and z must be finite and > 0");
     if (!(std::isfinite(beta) && beta > 2.0 && beta < 4.0)) return fail(PS_E_PARAM, "beta must lie in (2, 4)");
@@ -574,9 +615,8 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
     ProgBuilder a(N, (int64_t)nb * N);
     a.p.n_iter = C;
     for (int j = 0; j < C; ++j) a.p.scale[j] = scale[j];
-    a.op(ROP_KEEP_R, phi, nn(N), N)
-        .op(ROP_LOOP)
-        .op(ROP_EXP_KEEP, nullptr, 0, 0, 0, RF_ITER_SCALE)
+    a.op(ROP_LOOP)
+        .op(ROP_LOAD_PHASE, phi, nn(N), N, 0, RF_ITER_SCALE)
         .op(ROP_FFT_FWD)
         .op(ROP_MUL_TAB, H, 0, 0, N)
         .op(ROP_FFT_INV)
@@ -604,6 +644,7 @@ int fresnel_propagate(int N, double delta, double lambda, double z, const void *
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n)) return rc;
     if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
+    if (int rc = check_aligned({phi, I_out})) return rc;
     if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
         return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
     if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
@@ -641,6 +682,7 @@ int illumination_polychromatic(int N, double delta, double z, const void *phi_re
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n_real)) return rc;
     if (!phi_ref || !I_out || !lambdas) return fail(PS_E_NULL, "phi_ref, lambdas and I_out must be non-NULL");
+    if (int rc = check_aligned({phi_ref, I_out})) return rc;
     if (n_lambda < 1 || n_lambda > 4096) return fail(PS_E_SIZE, "n_lambda must lie in [1, 4096]");
     if (!finite_pos(delta) || !finite_pos(z) || !finite_pos(lambda_ref))
         return fail(PS_E_PARAM, "delta, z and lambda_ref must be finite and > 0");
@@ -767,6 +809,7 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n_real)) return rc;
     if (!I_in || !I_out || !radii) return fail(PS_E_NULL, "I_in, radii and I_out must be non-NULL");
+    if (int rc = check_aligned({I_in, I_out})) return rc;
     if (n_r < 1 || n_r > kRowMaxIter) return fail(PS_E_SIZE, "n_r must lie in [1, 64]");
     if (!finite_pos(delta)) return fail(PS_E_PARAM, "delta must be finite and > 0");
     for (int j = 0; j < n_r; ++j)
@@ -830,6 +873,7 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n)) return rc;
     if (!phi || !grad_I || !grad_phi_out) return fail(PS_E_NULL, "phi, grad_I and grad_phi_out must be non-NULL");
+    if (int rc = check_aligned({phi, grad_I, grad_phi_out})) return rc;
     if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
         return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
     if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
@@ -863,9 +907,8 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
         const char *gI = static_cast<const char *>(grad_I) + (size_t)b0 * rb1;
         // forward x-propagation (recomputed; nothing is kept between calls)
         ProgBuilder a(N, (int64_t)nb * N);
-        a.op(ROP_KEEP_R, ph, nn(N), N)
-            .op(ROP_LOOP)
-            .op(ROP_EXP_KEEP, nullptr, 0, 0, 0, 0, phase_scale)
+        a.op(ROP_LOOP)
+            .op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
             .op(ROP_FFT_FWD)
             .op(ROP_MUL_TAB, H)
             .op(ROP_FFT_INV)
@@ -921,6 +964,7 @@ int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out, d
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n)) return rc;
     if (!I || !m_out) return fail(PS_E_NULL, "I and m_out must be non-NULL");
+    if (int rc = check_aligned({I})) return rc;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const int64_t per = nn(N);
     const int nblk = block_count(per);
@@ -953,6 +997,7 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype, voi
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n)) return rc;
     if (!I || !I_target) return fail(PS_E_NULL, "I and I_target must be non-NULL");
+    if (int rc = check_aligned({I, I_target, grad_out})) return rc;
     const size_t rb = (size_t)nn(N) * real_bytes(dtype) * n;
     if (grad_out && (overlaps(grad_out, rb, I, rb) || overlaps(grad_out, rb, I_target, rb)))
         return fail(PS_E_ALIAS, "grad_out overlaps I or I_target");

@@ -48,7 +48,8 @@ SIGNATURES = {
     "ps_version": (_c_int, []),
     "ps_timing_enable": (_c_int, [_c_int]),
     "ps_timing_count": (_c_int, []),
-    "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp]),
+    "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp,
+                                 _dp]),
 }
 
 _lock = threading.Lock()
@@ -150,15 +151,16 @@ def timing_enable(on: bool = True) -> None:
 
 
 def timing_report() -> dict:
-    """{kernel name: {"ms": total, "launches": n, "bytes": algorithmic bytes}}
+    """{kernel name: {"ms": total, "launches": n, "bytes": algorithmic bytes, "flops": ...}}
     for the kernels launched while timing was enabled (waits for them)."""
     lib = load_library()
     out = {}
     for i in range(lib.ps_timing_count()):
         buf = ctypes.create_string_buffer(256)
-        ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
-        _check("ps_timing_entry", lib.ps_timing_entry(i, buf, 256, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
-        out[buf.value.decode()] = {"ms": ms.value, "launches": n.value, "bytes": b.value}
+        ms, n, b, f = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        _check("ps_timing_entry", lib.ps_timing_entry(i, buf, 256, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                                      ctypes.byref(f)))
+        out[buf.value.decode()] = {"ms": ms.value, "launches": n.value, "bytes": b.value, "flops": f.value}
     return out
 
 

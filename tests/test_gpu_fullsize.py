@@ -1,0 +1,229 @@
+"""GPU parity at the full sizes of the named workloads, through the same entry
+points and launch configuration that bench.py times.
+
+Where the FP64 oracle finishes in seconds at full size it is compared pixel
+by pixel (4096^2, 10000^2, 16384^2, 2048^2 and 8192^2 single-wavelength
+cases); otherwise properties that hold at any size are checked (mean
+intensity 1 by Parseval, the structure function of the screen against its
+exact discrete expectation, the sum over wavelengths equal to the weighted
+single-wavelength patterns, smearing preserving the mean and lowering m).
+
+FP32 intensity bar: RMS error <= 2e-5 and max error <= 1e-3 of the mean.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+F32_RMS, F32_MAX = 2e-5, 1e-3
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1301_0514_amd import scint
+    scint.load_library()
+    return scint
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1301_0514_amd import presets
+    return presets
+
+
+def errs(I, I_ref):
+    m = I_ref.mean()
+    d = I - I_ref
+    return float(np.sqrt(np.mean(d * d)) / m), float(np.abs(d).max() / m)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+# ------------------------------------------------------------ plain FP64 256^2
+@pytest.mark.parametrize("rho", [32.0, 8.0])
+def test_plain_fp64_256(S, P, oracle, rho):
+    c = P.PLAIN_FP64
+    z = P.z_for_rho(rho, c.lam)
+    I, phi = S.ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, c.lam, z, dtype=torch.float64, want_phi=True)
+    phi_ref = oracle.screen(c.N, c.R, c.beta, 1, 0)
+    I_ref = oracle.propagate(phi_ref, rho)
+    assert np.abs(host(phi)[0] - phi_ref).max() < 1e-11 * np.abs(phi_ref).max()
+    e_rms, e_max = errs(host(I)[0], I_ref)
+    assert e_max < 1e-11
+    m = S.ps_modulation_index(I)[0]
+    assert m == pytest.approx(oracle.modulation_index(I_ref), rel=1e-10)
+
+
+# ------------------------------------------------------------ 4096^2 single wavelength
+@pytest.mark.parametrize("R,seed", [(8.0, 1), (32.0, 2), (128.0, 4)])
+def test_single_4096(S, P, oracle, R, seed):
+    c = [x for x in P.SINGLE_4096 if x.R == R][0]
+    I = S.ps_screen_fresnel(c.N, 1.0, c.R, c.beta, seed, c.lam, c.z)
+    I_ref = oracle.propagate(oracle.screen(c.N, c.R, c.beta, seed, 0), c.rho)
+    e_rms, e_max = errs(host(I)[0], I_ref)
+    print("4096 R=%g seed=%d e_rms=%.2e e_max=%.2e" % (R, seed, e_rms, e_max))
+    assert e_rms < F32_RMS and e_max < F32_MAX
+
+
+# ------------------------------------------------------------ paper-scale grids
+@pytest.mark.parametrize("N,beta", [(10000, 11 / 3), (10000, 3.9), (16384, 11 / 3)])
+def test_paper_scale_vs_oracle(S, P, oracle, N, beta):
+    c = [x for x in P.PAPER_SCALE if x.N == N and abs(x.beta - beta) < 1e-9][0]
+    I = S.ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, c.lam, c.z)
+    I = host(I)[0]
+    I_ref = oracle.propagate(oracle.screen(c.N, c.R, c.beta, 1, 0), c.rho)
+    e_rms, e_max = errs(I, I_ref)
+    print("N=%d beta=%.3f e_rms=%.2e e_max=%.2e" % (N, beta, e_rms, e_max))
+    assert e_rms < F32_RMS and e_max < F32_MAX
+
+
+def _expected_D(oracle, N, R, beta, lags):
+    """Exact expectation of the structure function along x of one screen and
+    the standard deviation of its one-realisation estimate (each Fourier
+    mode's power is exponential; modes k and -k carry the same power)."""
+    A = oracle.spectrum(1.0, R, beta)
+    k = np.arange(N)
+    k = np.where(k < N // 2, k, k - N).astype(np.float64)
+    S1 = np.zeros(N)
+    S2 = np.zeros(N)
+    for i0 in range(0, N, 1024):
+        kx = k[i0:i0 + 1024]
+        k2 = kx[:, None] ** 2 + k[None, :] ** 2
+        with np.errstate(divide="ignore"):
+            s = A * (np.sqrt(k2) / N) ** (-beta)
+        s[~np.isfinite(s)] = 0.0
+        S1[i0:i0 + 1024] = s.sum(axis=1)
+        S2[i0:i0 + 1024] = (s * s).sum(axis=1)
+    E, SD = [], []
+    for lag in lags:
+        w = 2 * (1 - np.cos(2 * np.pi * k * lag / N))
+        E.append((w * S1).sum() / N ** 2)
+        SD.append(np.sqrt(2 * (w * w * S2).sum()) / N ** 2)
+    return np.array(E), np.array(SD)
+
+
+@pytest.mark.parametrize("N,beta", [(10000, 3.2), (10000, 3.1), (16384, 3.9)])
+def test_paper_scale_properties(S, P, oracle, N, beta):
+    c = [x for x in P.PAPER_SCALE if x.N == N and abs(x.beta - beta) < 1e-9][0]
+    I, phi = S.ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, c.lam, c.z, want_phi=True)
+    m, mean = S.ps_modulation_index(I, want_mean=True)
+    assert mean[0] == pytest.approx(1.0, abs=2e-6)
+    assert 0.3 < m[0] < 3.0
+    # structure function of the one realisation against the exact expectation,
+    # at lags inside the inertial range where one screen averages many cells
+    lags = [4, 8, 16]
+    f = phi[0]
+    D = [float(((torch.roll(f, -l, dims=1) - f).double() ** 2).mean()) for l in lags]
+    E, SD = _expected_D(oracle, N, c.R, beta, lags)
+    for d, e, sd in zip(D, E, SD):
+        print("N=%d beta=%.2f D=%.4g E=%.4g sd=%.3g" % (N, beta, d, e, sd))
+        assert abs(d - e) < 5 * sd + 1e-4 * e
+
+
+# ------------------------------------------------------------ batched polychromatic + smear
+def test_poly_8192_batch_properties(S, P):
+    c = P.POLY_8192
+    N = c.N
+    phi = S.ps_generate(N, 1.0, c.R_ref, c.beta, c.seed, 0, c.n_real)
+    I = S.illumination_polychromatic(phi, 1.0, c.z, c.lam_ref, c.lambdas)
+    m, mean = S.ps_modulation_index(I, want_mean=True)
+    for b in range(c.n_real):
+        assert mean[b] == pytest.approx(1.0, abs=2e-6)
+        assert 0.05 < m[b] < 1.5
+    ext = S.source_smear(I, 1.0, c.smear_radii)
+    me, meane = S.ps_modulation_index(ext.view(-1, N, N), want_mean=True)
+    me = np.array(me).reshape(c.n_real, len(c.smear_radii))
+    meane = np.array(meane).reshape(c.n_real, len(c.smear_radii))
+    assert np.abs(meane - 1).max() < 2e-6
+    for b in range(c.n_real):
+        # Sect. 4.1: the contrast falls as the source grows
+        assert all(me[b, j + 1] < me[b, j] < m[b] for j in range(len(c.smear_radii) - 1))
+    # realisation 0 of the batch equals the weighted single-wavelength patterns
+    acc = torch.zeros((1, N, N), dtype=torch.float64, device="cuda")
+    for lam in c.lambdas:
+        acc += S.illumination_polychromatic(phi[0:1], 1.0, c.z, c.lam_ref, [lam]).double() / len(c.lambdas)
+    d = (I[0:1].double() - acc).abs().max().item()
+    assert d < 2e-6 * acc.max().item()
+
+
+def test_poly_8192_two_wavelengths_vs_oracle(S, P, oracle):
+    c = P.POLY_8192
+    N = c.N
+    lams = [c.lambdas[0], c.lambdas[-1]]
+    w = [0.3, 0.7]
+    phi = S.ps_generate(N, 1.0, c.R_ref, c.beta, c.seed, 0, 1)
+    I = host(S.illumination_polychromatic(phi, 1.0, c.z, c.lam_ref, lams, w))[0]
+    phi_ref = oracle.screen(N, c.R_ref, c.beta, c.seed, 0)
+    I_ref = oracle.polychromatic(phi_ref, 1.0, c.z, c.lam_ref, lams, w)
+    e_rms, e_max = errs(I, I_ref)
+    print("8192 two wavelengths e_rms=%.2e e_max=%.2e" % (e_rms, e_max))
+    assert e_rms < F32_RMS and e_max < F32_MAX
+
+
+def test_smear_8192_vs_oracle(S, P, oracle):
+    c = P.POLY_8192
+    N = c.N
+    I = S.ps_screen_fresnel(N, 1.0, c.R_ref, c.beta, 3, c.lam_ref, c.z)
+    Rs = c.smear_radii[0]
+    ext = host(S.source_smear(I, 1.0, [Rs]))[0, 0]
+    ref = oracle.smear(host(I)[0], Rs)
+    assert np.abs(ext - ref).max() < 2e-6 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------ differentiation
+def test_grad_2048_vs_oracle(S, P, oracle):
+    g = P.GRAD_2048
+    nr = 2
+    lam, z = g.lam, g.z
+    It = torch.cat([S.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, P.GRAD_TARGET_SEED0 + i, lam, z) for i in range(nr)])
+    I, phi = S.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, 1, lam, z, first_realisation=0, n_real=nr, want_phi=True)
+    loss, gI = S.ps_l2_loss(I, It)
+    gphi, dots = S.fresnel_propagate_vjp(phi, 1.0, lam, z, gI, want_dot=True)
+    for b in range(nr):
+        phi_ref = oracle.screen(g.N, g.R, g.beta, 1, b)
+        It_ref = oracle.propagate(oracle.screen(g.N, g.R, g.beta, P.GRAD_TARGET_SEED0 + b, 0), g.rho)
+        I_ref = oracle.propagate(phi_ref, g.rho)
+        L_ref = ((I_ref - It_ref) ** 2).sum()
+        assert loss[b] == pytest.approx(L_ref, rel=1e-4)
+        g_ref = oracle.propagate_vjp(phi_ref, g.rho, 1.0, 2 * (I_ref - It_ref))
+        gg = host(gphi)[b]
+        rel = np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref)
+        print("grad 2048 b=%d rel L2 err %.2e" % (b, rel))
+        assert rel < 1e-3
+        dlogR_ref = (2 - g.beta) / 2 * (phi_ref * g_ref).sum()
+        dlogR = (2 - g.beta) / 2 * dots[b]
+        assert dlogR == pytest.approx(dlogR_ref, rel=1e-3)
+
+
+def test_grad_fp64_256_finite_differences(S):
+    # FP64 subproblem: 256^2, rho = 6, R_diff = 3, central differences h = 1e-4
+    N, rho, R, beta, lam = 256, 6.0, 3.0, 11 / 3, 5e-7
+    z = 2 * np.pi * rho ** 2 / lam
+    f64 = torch.float64
+    It = S.ps_screen_fresnel(N, 1.0, R, beta, 1000, lam, z, dtype=f64)
+    phi = S.ps_generate(N, 1.0, R, beta, 1, 0, 1, dtype=f64)
+
+    def loss_of(p):
+        I = S.fresnel_propagate(p, 1.0, lam, z)
+        return float(((I - It) ** 2).sum())
+
+    I = S.fresnel_propagate(phi, 1.0, lam, z)
+    _, gI = S.ps_l2_loss(I, It)
+    g, dots = S.fresnel_propagate_vjp(phi, 1.0, lam, z, gI, want_dot=True)
+    g = host(g)[0]
+    rng = np.random.default_rng(7)
+    h = 1e-4
+    for (py, px) in rng.integers(0, N, size=(64, 2)):
+        p1 = phi.clone(); p1[0, py, px] += h
+        p0 = phi.clone(); p0[0, py, px] -= h
+        fd = (loss_of(p1) - loss_of(p0)) / (2 * h)
+        assert fd == pytest.approx(g[py, px], rel=1e-6, abs=1e-7 * np.abs(g).max())
+    # dL/dlog R_diff: the screen scales as R_diff^((2 - beta)/2)
+    Lp = loss_of(S.ps_generate(N, 1.0, R * np.exp(h), beta, 1, 0, 1, dtype=f64))
+    Lm = loss_of(S.ps_generate(N, 1.0, R * np.exp(-h), beta, 1, 0, 1, dtype=f64))
+    assert (Lp - Lm) / (2 * h) == pytest.approx((2 - beta) / 2 * dots[0], rel=1e-6)
