@@ -68,6 +68,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="time eager calls instead of replays of the captured step")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="first copy this many GB device-to-device with one plain copy kernel, as the "
                          "reference of known size for the FETCH_SIZE/WRITE_SIZE counters")
@@ -113,28 +115,49 @@ def main(argv=None) -> int:
         scint.source_smear(I_sum, 1.0, radii, out=I_ext)
 
     log("warmup %d steps (N=%d, %d screens, %d wavelengths, %d radii)" % (args.warmup, N, n_real, n_lam, len(radii)))
-    for _ in range(args.warmup):
-        step()
+    # the whole step (screens, all wavelengths, smears) is captured into one
+    # HIP graph after the warm-up; the timed region replays it
+    stream = torch.cuda.Stream()
+    graph = None
+    if args.graph:
+        graph, stream = scint.capture_graph(step, warmup=args.warmup, stream=stream)
+    else:
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                step()
     torch.cuda.synchronize()
 
-    scint.timing_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
+    with torch.cuda.stream(stream):
+        ev0.record()
+        for _ in range(args.steps):
+            if graph is not None:
+                graph.replay()
+            else:
+                step()
+        ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rep = scint.timing_report()
-    scint.timing_enable(False)
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
     units = float(N) * N * n_lam * n_real
     value = units / (ms_step / 1e3)
-    log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms_step, wall))
+    log("timed %d steps (%s): %.2f ms/step (wall %.2f s)" % (args.steps, "graph replay" if graph else "eager",
+                                                          ms_step, wall))
+    # per-kernel durations: the same step run eagerly with the library's
+    # event timing on (events cannot be recorded per kernel inside a replay)
+    scint.timing_enable(True)
+    with torch.cuda.stream(stream):
+        for _ in range(args.steps):
+            step()
+    torch.cuda.synchronize()
+    rep = scint.timing_report()
+    scint.timing_enable(False)
+    ms_eager = sum(v["ms"] for v in rep.values()) / args.steps
+    log("instrumented eager steps: %.2f ms of kernels per step" % ms_eager)
 
     # dominant kernel and its roofline.  Row passes that run FFTs are bound by
     # VALU issue (their HBM traffic is a fraction of the bandwidth); the
@@ -186,6 +209,8 @@ def main(argv=None) -> int:
                    "N": N, "n_real": n_real, "n_lambda": n_lam, "smear_radii_px": radii,
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "timing": "graph replay of the whole step" if graph is not None else "eager calls",
+        "kernel_ms_per_step_eager": ms_eager,
         "step_algorithmic_GB": step_bytes / 1e9,
         "step_frac_of_hbm_roofline": (step_bytes / (ms_step / 1e3)) / (HBM_PEAK_GBS * 1e9),
         "kernels": kernels,

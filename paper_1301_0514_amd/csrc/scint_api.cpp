@@ -113,8 +113,10 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 // ------------------------------------------------------------ device caches
 struct DeviceCache {
     std::map<std::pair<int, int>, void *> twiddles;  // (L, dtype) -> table
-    std::map<std::tuple<int, uint64_t, int>, void *> disks;  // (N, radius bits, dtype) -> spectrum
+    // (N, dtype, radius bits...) -> n_r contiguous disk spectra
+    std::map<std::pair<std::pair<int, int>, std::vector<uint64_t>>, void *> disks;
     std::map<hipStream_t, std::pair<void *, size_t>> workspace;
+    size_t budget = 0;  // workspace bytes a call plans for, fixed at first use
 };
 
 std::mutex g_mutex;
@@ -417,12 +419,20 @@ void set_noise(RowProgram &p, int N, double R, double beta, uint64_t seed, uint3
 int64_t nn(int N) { return (int64_t)N * N; }
 
 // Upper bound on workspace bytes a call plans for (whole-batch processing is
-// split into chunks above it).
+// split into chunks above it): half the free device memory at the first call
+// on the device, at most 48 GiB.  Fixed afterwards, so that a given call
+// always takes the same chunking (and no call queries the device again).
 size_t workspace_budget() {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return (size_t)8 << 30;
-    const size_t cap = (size_t)48 << 30;
-    return std::min(cap, free_b / 2);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return (size_t)8 << 30;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto &dc = g_cache[dev];
+    if (dc.budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
+        dc.budget = std::max<size_t>((size_t)1 << 30, std::min<size_t>((size_t)48 << 30, free_b / 2));
+    }
+    return dc.budget;
 }
 
 // ------------------------------------------------------------ pipelines
@@ -736,14 +746,16 @@ int illumination_polychromatic(int N, double delta, double z, const void *phi_re
     return PS_OK;
 }
 
-// Spectrum of the normalised disk of radius R pixels, divided by N^2 (the
-// inverse-transform normalisation), as a real N x N table indexed [kx][ky].
-static int get_disk_spectrum(int N, double Rpx, int dtype, hipStream_t stream, const void **out) {
+// Spectra of the normalised disks of radii Rpx[j] pixels, divided by N^2 (the
+// inverse-transform normalisation), as n_r contiguous real N x N tables
+// indexed [kx][ky]; cached per (N, dtype, radii).
+static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hipStream_t stream,
+                            const void **out) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
-    uint64_t bits;
-    std::memcpy(&bits, &Rpx, sizeof(bits));
-    auto key = std::make_tuple(N, bits, dtype);
+    std::vector<uint64_t> bits(Rpx.size());
+    for (size_t j = 0; j < Rpx.size(); ++j) std::memcpy(&bits[j], &Rpx[j], sizeof(uint64_t));
+    auto key = std::make_pair(std::make_pair(N, dtype), bits);
     {
         std::lock_guard<std::mutex> lock(g_mutex);
         auto &dc = g_cache[dev];
@@ -753,53 +765,56 @@ static int get_disk_spectrum(int N, double Rpx, int dtype, hipStream_t stream, c
             return PS_OK;
         }
     }
-    // pixel count of the disk, same test as the disk image kernel
-    const double r2 = Rpx * Rpx;
-    double count = 0.0;
-    for (int y = 0; y < N; ++y) {
-        const double dy = y < N / 2 ? y : y - N;
-        if (dy * dy > r2) continue;
-        for (int x = 0; x < N; ++x) {
-            const double dx = x < N / 2 ? x : x - N;
-            if (dx * dx + dy * dy <= r2) count += 1.0;
-        }
-    }
     const size_t rb = (size_t)nn(N) * real_bytes(dtype);
     const size_t cb = 2 * rb;
-    void *tab = nullptr;
-    if (hipMalloc(&tab, rb) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of disk spectrum failed");
+    void *block = nullptr;
+    if (hipMalloc(&block, rb * Rpx.size()) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of disk spectra failed");
     void *tmp = nullptr;
     if (hipMalloc(&tmp, 2 * cb) != hipSuccess) {
-        (void)hipFree(tab);
+        (void)hipFree(block);
         return fail(PS_E_ALLOC, "hipMalloc of disk workspace failed");
     }
     char *W1 = static_cast<char *>(tmp), *W2 = W1 + cb;
     int rc = PS_OK;
-    hipError_t e = launch_disk_image(tab, N, r2, 1.0 / count, dtype == PS_F64, stream);
-    if (e != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk image: ") + hipGetErrorString(e));
-    if (!rc) {
-        ProgBuilder a(N, N);
-        a.op(ROP_LOAD_R, tab, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, 0, N);
-        rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream);
+    for (size_t j = 0; j < Rpx.size() && !rc; ++j) {
+        // pixel count of the disk, same test as the disk image kernel
+        const double r2 = Rpx[j] * Rpx[j];
+        double count = 0.0;
+        for (int y = 0; y < N; ++y) {
+            const double dy = y < N / 2 ? y : y - N;
+            if (dy * dy > r2) continue;
+            for (int x = 0; x < N; ++x) {
+                const double dx = x < N / 2 ? x : x - N;
+                if (dx * dx + dy * dy <= r2) count += 1.0;
+            }
+        }
+        char *tab = static_cast<char *>(block) + j * rb;
+        hipError_t e = launch_disk_image(tab, N, r2, 1.0 / count, dtype == PS_F64, stream);
+        if (e != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk image: ") + hipGetErrorString(e));
+        if (!rc) {
+            ProgBuilder a(N, N);
+            a.op(ROP_LOAD_R, tab, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, 0, N);
+            rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream);
+        }
+        if (!rc) rc = transpose(W1, W2, N, 1, 2 * (int)real_bytes(dtype), stream);
+        if (!rc) {
+            ProgBuilder b(N, N);
+            b.op(ROP_LOAD_C, W2, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_R, tab, 0, N, 0, 0, 1.0 / (double)nn(N));
+            rc = run_row<ProgFwdReTag>(dtype, N, b.p, b.n, stream);
+        }
     }
-    if (!rc) rc = transpose(W1, W2, N, 1, 2 * (int)real_bytes(dtype), stream);
     if (!rc) {
-        ProgBuilder b(N, N);
-        b.op(ROP_LOAD_C, W2, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_R, tab, 0, N, 0, 0, 1.0 / (double)nn(N));
-        rc = run_row<ProgFwdReTag>(dtype, N, b.p, b.n, stream);
-    }
-    if (!rc) {
-        e = hipStreamSynchronize(stream);
+        hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk spectrum: ") + hipGetErrorString(e));
     }
     (void)hipFree(tmp);
     if (rc) {
-        (void)hipFree(tab);
+        (void)hipFree(block);
         return rc;
     }
     std::lock_guard<std::mutex> lock(g_mutex);
-    g_cache[dev].disks[key] = tab;
-    *out = tab;
+    g_cache[dev].disks[key] = block;
+    *out = block;
     return PS_OK;
 }
 
@@ -818,28 +833,23 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
     if (overlaps(I_in, rb1 * n_real, I_out, rb1 * n_real * n_r) && !(n_r == 1 && I_in == I_out))
         return fail(PS_E_ALIAS, "I_out overlaps I_in (allowed only in place with n_r == 1)");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    std::vector<const void *> disk(n_r);
-    for (int j = 0; j < n_r; ++j)
-        if (int rc = get_disk_spectrum(N, radii[j] / delta, dtype, stream, &disk[j])) return rc;
-    // the loop over radii indexes the disk tables through iter_stride, so
-    // they must be equally spaced; copy them into one block when they are not
+    std::vector<double> rpx(n_r);
+    for (int j = 0; j < n_r; ++j) rpx[j] = radii[j] / delta;
+    const void *D = nullptr;
+    if (int rc = get_disk_spectra(N, rpx, dtype, stream, &D)) return rc;
     const size_t cbytes = 2 * rb1;
     const size_t budget = workspace_budget();
-    const int nb_max = (int)std::max<size_t>(1, (budget > rb1 * n_r ? budget - rb1 * n_r : 0) /
-                                                    (cbytes * (2 + 2 * (size_t)n_r)));
+    const int nb_max = (int)std::max<size_t>(1, budget / (cbytes * (2 + 2 * (size_t)n_r)));
     for (int b0 = 0; b0 < n_real; b0 += nb_max) {
         const int nb = std::min(nb_max, n_real - b0);
         void *ws = nullptr;
-        if (int rc = get_workspace(stream, cbytes * nb * (2 + 2 * (size_t)n_r) + rb1 * n_r + 4096, &ws)) return rc;
+        if (int rc = get_workspace(stream, cbytes * nb * (2 + 2 * (size_t)n_r) + 4096, &ws)) return rc;
         Carver c;
         char *base = static_cast<char *>(ws);
-        char *D = base + c.take(rb1 * n_r);
         char *W1 = base + c.take(cbytes * nb);
         char *W2 = base + c.take(cbytes * nb);
         char *V1 = base + c.take(cbytes * nb * n_r);
         char *V2 = base + c.take(cbytes * nb * n_r);
-        for (int j = 0; j < n_r; ++j)
-            HIP_TRY(hipMemcpyAsync(D + j * rb1, disk[j], rb1, hipMemcpyDeviceToDevice, stream));
         const char *Iin = static_cast<const char *>(I_in) + (size_t)b0 * rb1;
         ProgBuilder a(N, (int64_t)nb * N);
         a.op(ROP_LOAD_R, Iin, nn(N), N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, nn(N), N);

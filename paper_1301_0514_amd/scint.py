@@ -277,6 +277,25 @@ def ps_l2_loss(I: torch.Tensor, I_target: torch.Tensor, want_grad=True):
     return [loss[i] for i in range(n)], grad
 
 
+# ------------------------------------------------------------------ graphs
+def capture_graph(fn, warmup: int = 1, stream: torch.cuda.Stream | None = None):
+    """Capture fn() (a sequence of libscint calls on the current stream) into
+    a HIP graph.  fn runs `warmup` times first on the capture stream, so that
+    the library's per-stream workspace and its cached tables exist and the
+    captured calls allocate nothing.  Returns (graph, stream); replay with
+    graph.replay() under `with torch.cuda.stream(stream)`."""
+    stream = stream or torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, warmup)):
+            fn()
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        fn()
+    stream.synchronize()
+    return g, stream
+
+
 # ------------------------------------------------------------------ autograd
 class FresnelIntensity(torch.autograd.Function):
     """I = fresnel_propagate(phi) with the hand-written adjoint as backward."""
