@@ -216,6 +216,13 @@ def main(argv=None) -> int:
         "kernels": kernels,
     }
 
+    # FFT plans the tuner chose (times: one propagation row pass per plan)
+    plans = {}
+    for n_ in (N, 2048, 4096, 10000, 16384):
+        v_, ms_ = scint.plan_variant(n_)
+        plans[str(n_)] = {"variant": v_, "tuner_ms": ms_}
+    out["fft_plans"] = plans
+
     # ---------------------------------------------------------------- CPU baseline + accuracy
     if not args.no_cpu_baseline:
         import oracle as O

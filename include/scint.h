@@ -193,6 +193,27 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
                void *grad_out, double *loss_out, void *hip_stream);
 
 /*
+ * FFT plan variants and the plan tuner.  The large FP32 sizes (2048, 4096,
+ * 8192, 10000, 16384) have several compiled Stockham plans (radix orders and
+ * elements per thread).  The first FP32 call of such a size on a device times
+ * each plan on a propagation row pass over scratch data (hipMalloc of
+ * <= 200 MB, a private stream, synchronised) and keeps the fastest; it keeps
+ * plan 0 unless another is faster by more than 3%.  Different plans round
+ * differently (within FP32 rounding), so pin a plan for bitwise-reproducible
+ * results across processes: environment SCINT_PLAN_VARIANT=<v> or
+ * ps_set_plan_variant.  FP64 always uses plan 0.
+ *   ps_num_plan_variants  number of plans of N for dtype (0 if unsupported)
+ *   ps_plan_variant       plan in use (tuning it now if not yet chosen);
+ *                         ms_out, optional host array of
+ *                         ps_num_plan_variants(N, dtype) floats, receives the
+ *                         tuner's times (-1 where not timed)
+ *   ps_set_plan_variant   pins plan `variant`, or -1 to return to tuning
+ */
+int ps_num_plan_variants(int N, int dtype);
+int ps_plan_variant(int N, int dtype, int *variant_out, float *ms_out);
+int ps_set_plan_variant(int N, int dtype, int variant);
+
+/*
  * Kernel timing (instrumentation).  While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the stream it runs on,
  * and per kernel name the library accumulates the event-measured duration,

@@ -15,7 +15,10 @@
 
 namespace scint {
 
-template <int L> struct Plan;  // only the sizes below exist
+// Plan<L, V>: variant V of the plan for length L.  Variant 0 exists for every
+// supported size; the large FP32 sizes have alternatives that the run-time
+// tuner times on first use.
+template <int L, int V = 0> struct Plan;  // only the sizes below exist
 
 constexpr bool plan_ok(int L, int E, const int *R, int ns) {
     int prod = 1;
@@ -26,8 +29,8 @@ constexpr bool plan_ok(int L, int E, const int *R, int ns) {
     return prod == L && L % E == 0 && L / E <= 1024;
 }
 
-#define SCINT_PLAN(L_, E_, ...)                                                 \
-    template <> struct Plan<L_> {                                               \
+#define SCINT_PLAN_V(L_, V_, E_, ...)                                           \
+    template <> struct Plan<L_, V_> {                                           \
         static constexpr int L = L_;                                            \
         static constexpr int E = E_;                                            \
         static constexpr int R[] = {__VA_ARGS__};                               \
@@ -36,7 +39,7 @@ constexpr bool plan_ok(int L, int E, const int *R, int ns) {
         static_assert(plan_ok(L_, E_, R, NS),                                   \
                       "radices must multiply to L and each divide E");          \
     };
-
+#define SCINT_PLAN(L_, E_, ...) SCINT_PLAN_V(L_, 0, E_, __VA_ARGS__)
 // expands a size list given through another macro
 #define SCINT_PLAN_EXPAND(...) SCINT_PLAN(__VA_ARGS__)
 
@@ -48,22 +51,10 @@ SCINT_PLAN(128, 16, 16, 8)
 SCINT_PLAN(256, 16, 16, 16)
 SCINT_PLAN(512, 8, 8, 8, 8)
 SCINT_PLAN(1024, 16, 16, 16, 4)
-#ifndef SCINT_PLAN_2048
-#define SCINT_PLAN_2048 16, 16, 16, 8
-#endif
-SCINT_PLAN_EXPAND(2048, SCINT_PLAN_2048)
-#ifndef SCINT_PLAN_4096
-#define SCINT_PLAN_4096 32, 32, 8, 16
-#endif
-SCINT_PLAN_EXPAND(4096, SCINT_PLAN_4096)
-#ifndef SCINT_PLAN_8192
-#define SCINT_PLAN_8192 32, 32, 32, 8
-#endif
-SCINT_PLAN_EXPAND(8192, SCINT_PLAN_8192)
-#ifndef SCINT_PLAN_16384
-#define SCINT_PLAN_16384 32, 32, 32, 16
-#endif
-SCINT_PLAN_EXPAND(16384, SCINT_PLAN_16384)
+SCINT_PLAN(2048, 16, 16, 16, 8)
+SCINT_PLAN(4096, 32, 32, 8, 16)
+SCINT_PLAN(8192, 32, 32, 32, 8)
+SCINT_PLAN(16384, 32, 32, 32, 16)
 // 2^a 5^b
 SCINT_PLAN(40, 20, 4, 10)
 SCINT_PLAN(80, 20, 4, 20)
@@ -80,13 +71,29 @@ SCINT_PLAN(2560, 20, 4, 4, 4, 4, 10)
 SCINT_PLAN(4000, 20, 20, 20, 10)
 SCINT_PLAN(5000, 10, 10, 10, 10, 5)
 SCINT_PLAN(8000, 20, 20, 20, 20)
-#ifndef SCINT_PLAN_10000
-#define SCINT_PLAN_10000 10, 10, 10, 10, 10
-#endif
-SCINT_PLAN_EXPAND(10000, SCINT_PLAN_10000)
+SCINT_PLAN(10000, 10, 10, 10, 10, 10)
+
+// alternatives timed by the tuner (FP32)
+SCINT_PLAN_V(2048, 1, 16, 16, 8, 16)
+SCINT_PLAN_V(4096, 1, 16, 16, 16, 16)
+SCINT_PLAN_V(4096, 2, 32, 32, 16, 8)
+SCINT_PLAN_V(8192, 1, 16, 16, 8, 8, 8)
+SCINT_PLAN_V(8192, 2, 32, 32, 8, 32)
+SCINT_PLAN_V(10000, 1, 20, 20, 20, 5, 5)
+SCINT_PLAN_V(16384, 1, 32, 16, 32, 32)
+SCINT_PLAN_V(16384, 2, 32, 32, 16, 32)
 
 #undef SCINT_PLAN_EXPAND
 #undef SCINT_PLAN
+#undef SCINT_PLAN_V
+
+// Number of plan variants of length L (FP32; FP64 uses variant 0 only).
+constexpr int plan_variants(int L) {
+    return (L == 4096 || L == 8192 || L == 16384) ? 3 : (L == 2048 || L == 10000) ? 2 : 1;
+}
+
+// X(L, V) for every FP32 variant beyond 0
+#define SCINT_VARIANTS_F32(X) X(2048, 1) X(4096, 1) X(4096, 2) X(8192, 1) X(8192, 2) X(10000, 1) X(16384, 1) X(16384, 2)
 
 // Sizes in ascending order, per precision (FP64 stops at 8192 because a
 // 16384-point complex128 row does not fit in the 160 KB of LDS).
@@ -98,28 +105,30 @@ SCINT_PLAN_EXPAND(10000, SCINT_PLAN_10000)
 
 // Number of entries of the per-stage twiddle tables of a plan: stage s >= 1
 // holds W_{Ns R}^{r k} for k < Ns and r < R, i.e. Ns R entries.
-template <int L> constexpr int twiddle_count() {
+template <int L, int V = 0> constexpr int twiddle_count() {
+    using P = Plan<L, V>;
     int n = 0, ns = 1;
-    for (int s = 0; s < Plan<L>::NS; ++s) {
-        if (s > 0) n += ns * Plan<L>::R[s];
-        ns *= Plan<L>::R[s];
+    for (int s = 0; s < P::NS; ++s) {
+        if (s > 0) n += ns * P::R[s];
+        ns *= P::R[s];
     }
     return n;
 }
 
 // Offset of stage s's table inside the concatenated twiddle array.
-template <int L> constexpr int twiddle_offset(int stage) {
+template <int L, int V = 0> constexpr int twiddle_offset(int stage) {
+    using P = Plan<L, V>;
     int n = 0, ns = 1;
     for (int s = 0; s < stage; ++s) {
-        if (s > 0) n += ns * Plan<L>::R[s];
-        ns *= Plan<L>::R[s];
+        if (s > 0) n += ns * P::R[s];
+        ns *= P::R[s];
     }
     return n;
 }
 
-template <int L> constexpr int stage_ns(int stage) {
+template <int L, int V = 0> constexpr int stage_ns(int stage) {
     int ns = 1;
-    for (int s = 0; s < stage; ++s) ns *= Plan<L>::R[s];
+    for (int s = 0; s < stage; ++s) ns *= Plan<L, V>::R[s];
     return ns;
 }
 

@@ -16,21 +16,27 @@
 
 namespace scint {
 
-template <int L>
+template <int L, int V>
 static hipError_t launch_one(const RowProgram &prog, const void *tw, hipStream_t stream) {
-    using Cfg = RowCfg<SCINT_REAL, L>;
+    using Cfg = RowCfg<SCINT_REAL, L, V>;
     const int grid = (prog.total_rows + Cfg::B - 1) / Cfg::B;
-    hipLaunchKernelGGL((row_kernel<SCINT_REAL, L, SCINT_PROG>), dim3(grid), dim3(Cfg::THREADS), 0, stream,
+    hipLaunchKernelGGL((row_kernel<SCINT_REAL, L, V, SCINT_PROG>), dim3(grid), dim3(Cfg::THREADS), 0, stream,
                        prog, static_cast<const cpx<SCINT_REAL> *>(tw));
     return hipGetLastError();
 }
 
 template <>
-hipError_t launch_row<SCINT_REAL, SCINT_CAT(SCINT_PROG, Tag)>(int L, const RowProgram &prog, const void *tw,
+hipError_t launch_row<SCINT_REAL, SCINT_CAT(SCINT_PROG, Tag)>(int L, int V, const RowProgram &prog, const void *tw,
                                                                hipStream_t stream) {
 #define SCINT_CASE(LL) \
     case LL:           \
-        return launch_one<LL>(prog, tw, stream);
+        if (V == 0) return launch_one<LL, 0>(prog, tw, stream); \
+        break;
+#define SCINT_VCASE(LL, VV) \
+    if (L == LL && V == VV) return launch_one<LL, VV>(prog, tw, stream);
+#if !SCINT_IS_F64
+    SCINT_VARIANTS_F32(SCINT_VCASE)
+#endif
     switch (L) {
 #if SCINT_IS_F64
         SCINT_SIZES_F64(SCINT_CASE)
@@ -38,9 +44,11 @@ hipError_t launch_row<SCINT_REAL, SCINT_CAT(SCINT_PROG, Tag)>(int L, const RowPr
         SCINT_SIZES_F32(SCINT_CASE)
 #endif
     default:
-        return hipErrorInvalidValue;
+        break;
     }
+    return hipErrorInvalidValue;
 #undef SCINT_CASE
+#undef SCINT_VCASE
 }
 
 }  // namespace scint

@@ -17,8 +17,8 @@ namespace scint {
 constexpr int kLdsPadShift = SCINT_LDS_PAD_SHIFT;
 __device__ __forceinline__ int lds_index(int p) { return kLdsPadShift > 0 ? p + (p >> kLdsPadShift) : p; }
 
-template <typename Real, int L> struct RowCfg {
-    using P = Plan<L>;
+template <typename Real, int L, int V = 0> struct RowCfg {
+    using P = Plan<L, V>;
     static constexpr int T = P::T;
     static constexpr int LDS_STRIDE = kLdsPadShift > 0 ? L + (L >> kLdsPadShift) : L;
     static constexpr int ELEM = 2 * (int)sizeof(Real);
@@ -42,12 +42,12 @@ template <typename Real, int L> struct RowCfg {
 };
 
 // ---------------------------------------------------------------- FFT
-template <typename Real, int L, int s>
-__device__ __forceinline__ void fft_stage(cpx<Real> (&v)[Plan<L>::E], cpx<Real> *lds, int t,
+template <typename Real, int L, int V, int s>
+__device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
                                           const cpx<Real> *__restrict__ tw) {
-    using P = Plan<L>;
+    using P = Plan<L, V>;
     constexpr int E = P::E, T = P::T, R = P::R[s], Q = E / R;
-    constexpr int Ns = stage_ns<L>(s);
+    constexpr int Ns = stage_ns<L, V>(s);
     constexpr bool last = (s == P::NS - 1);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -60,7 +60,7 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[Plan<L>::E], cpx<Real> 
             // keep the compiler from hoisting twiddle loads out of loops over
             // wavelengths (they would stay live in registers across FFTs)
             asm volatile("" ::: "memory");
-            const cpx<Real> *w = tw + twiddle_offset<L>(s) + k * R;
+            const cpx<Real> *w = tw + twiddle_offset<L, V>(s) + k * R;
 #pragma unroll
             for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
         }
@@ -79,15 +79,15 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[Plan<L>::E], cpx<Real> 
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = lds[lds_index(t + m * T)];
         __syncthreads();
-        fft_stage<Real, L, s + 1>(v, lds, t, tw);
+        fft_stage<Real, L, V, s + 1>(v, lds, t, tw);
     }
 }
 
 // Forward DFT of the register row (natural order in, natural order out).
-template <typename Real, int L>
-__device__ __forceinline__ void fft_forward(cpx<Real> (&v)[Plan<L>::E], cpx<Real> *lds, int t,
+template <typename Real, int L, int V>
+__device__ __forceinline__ void fft_forward(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
                                             const cpx<Real> *__restrict__ tw) {
-    fft_stage<Real, L, 0>(v, lds, t, tw);
+    fft_stage<Real, L, V, 0>(v, lds, t, tw);
 }
 
 // ---------------------------------------------------------------- pointwise
@@ -183,8 +183,8 @@ template <class Ops> constexpr int find_endloop(int i) {
     return Ops::n;
 }
 
-template <typename Real, int L> struct RowState {
-    static constexpr int E = Plan<L>::E;
+template <typename Real, int L, int V> struct RowState {
+    static constexpr int E = Plan<L, V>::E;
     cpx<Real> v[E];
     Real acc[E];
     Real keep[E];
@@ -197,9 +197,9 @@ template <typename Real, int L> struct RowState {
     bool valid;
 };
 
-template <typename Real, int L, int CODE>
-__device__ __forceinline__ void exec_op(RowState<Real, L> &st, const RowOp &op) {
-    constexpr int E = Plan<L>::E, T = Plan<L>::T;
+template <typename Real, int L, int V, int CODE>
+__device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &op) {
+    constexpr int E = Plan<L, V>::E, T = Plan<L, V>::T;
     auto &v = st.v;
     const bool valid = st.valid;
     const int64_t off = (int64_t)st.batch * op.batch_stride + (int64_t)st.it * op.iter_stride +
@@ -231,12 +231,12 @@ __device__ __forceinline__ void exec_op(RowState<Real, L> &st, const RowOp &op) 
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)st.keep[m]);
     } else if constexpr (CODE == ROP_FFT_FWD) {
-        fft_forward<Real, L>(v, st.lds, st.t, st.tw);
+        fft_forward<Real, L, V>(v, st.lds, st.t, st.tw);
     } else if constexpr (CODE == ROP_FFT_INV) {
         // IDFT(v) = conj(DFT(conj(v)))
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
-        fft_forward<Real, L>(v, st.lds, st.t, st.tw);
+        fft_forward<Real, L, V>(v, st.lds, st.t, st.tw);
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
     } else if constexpr (CODE == ROP_MUL_TAB) {
@@ -329,31 +329,31 @@ __device__ __forceinline__ void exec_op(RowState<Real, L> &st, const RowOp &op) 
     }
 }
 
-template <typename Real, int L, class Ops, int I, int End>
-__device__ __forceinline__ void run_ops(RowState<Real, L> &st) {
+template <typename Real, int L, int V, class Ops, int I, int End>
+__device__ __forceinline__ void run_ops(RowState<Real, L, V> &st) {
     if constexpr (I < End) {
         constexpr int c = Ops::code[I];
         if constexpr (c == ROP_LOOP) {
             constexpr int e = find_endloop<Ops>(I);
 #pragma clang loop unroll(disable)
-            for (st.it = 0; st.it < st.prog->n_iter; ++st.it) run_ops<Real, L, Ops, I + 1, e>(st);
+            for (st.it = 0; st.it < st.prog->n_iter; ++st.it) run_ops<Real, L, V, Ops, I + 1, e>(st);
             st.it = 0;
-            run_ops<Real, L, Ops, e + 1, End>(st);
+            run_ops<Real, L, V, Ops, e + 1, End>(st);
         } else {
-            exec_op<Real, L, c>(st, st.prog->op[I]);
-            run_ops<Real, L, Ops, I + 1, End>(st);
+            exec_op<Real, L, V, c>(st, st.prog->op[I]);
+            run_ops<Real, L, V, Ops, I + 1, End>(st);
         }
     }
 }
 
-template <typename Real, int L, class Ops>
-__global__ __launch_bounds__((RowCfg<Real, L>::THREADS))
-__attribute__((amdgpu_waves_per_eu(RowCfg<Real, L>::WAVES_PER_EU))) void row_kernel(const RowProgram prog,
-                                                                        const cpx<Real> *__restrict__ tw) {
-    using Cfg = RowCfg<Real, L>;
-    constexpr int E = Plan<L>::E, T = Plan<L>::T, B = Cfg::B;
+template <typename Real, int L, int V, class Ops>
+__global__ __launch_bounds__((RowCfg<Real, L, V>::THREADS))
+__attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_kernel(const RowProgram prog,
+                                                                           const cpx<Real> *__restrict__ tw) {
+    using Cfg = RowCfg<Real, L, V>;
+    constexpr int E = Plan<L, V>::E, T = Plan<L, V>::T, B = Cfg::B;
     __shared__ __align__(16) unsigned char lds_raw[Cfg::LDS_BYTES];
-    RowState<Real, L> st;
+    RowState<Real, L, V> st;
     st.prog = &prog;
     st.tid = threadIdx.x;
     const int bsub = st.tid / T;
@@ -371,7 +371,7 @@ __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L>::WAVES_PER_EU))) void row_ker
         st.v[m] = {(Real)0, (Real)0};
         st.acc[m] = (Real)0;
     }
-    run_ops<Real, L, Ops, 0, Ops::n>(st);
+    run_ops<Real, L, V, Ops, 0, Ops::n>(st);
 }
 
 // The row programs used by the library.  Each name lists its op codes; the

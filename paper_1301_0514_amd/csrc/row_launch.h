@@ -20,19 +20,16 @@ struct ProgInvReTag;
 struct ProgVjpYTag;
 struct ProgVjpXTag;
 
-// Launches program Tag on total_rows rows of length L (the grid size N);
-// tw is the device twiddle table of the length-L plan in the same precision.
-// Returns hipErrorInvalidValue for an unsupported L.
+// Launches program Tag on total_rows rows of length L (the grid size N) with
+// plan variant V; tw is the device twiddle table of that plan in the same
+// precision.  Returns hipErrorInvalidValue for an unsupported (L, V).
 template <typename Real, class Tag>
-hipError_t launch_row(int L, const RowProgram &prog, const void *tw, hipStream_t stream);
+hipError_t launch_row(int L, int V, const RowProgram &prog, const void *tw, hipStream_t stream);
 
-// Rows handled by one workgroup and threads per workgroup, for reporting.
-template <typename Real> int row_threads(int L);
-
-// Number of twiddle entries of the length-L plan (0 if unsupported), and a
-// builder that fills them: W_{Ns R}^{r k} = exp(-2 pi i r k / (Ns R)) for
-// every stage s >= 1, k < Ns, r < R, evaluated in extended precision.
-int twiddle_entries(int L);
-bool build_twiddles(int L, double *out_ri /* 2 * twiddle_entries(L) */);
+// Number of twiddle entries of plan (L, V) (0 if unsupported), and a builder
+// that fills them: W_{Ns R}^{r k} = exp(-2 pi i r k / (Ns R)) for every stage
+// s >= 1, k < Ns, r < R, evaluated in extended precision.
+int twiddle_entries(int L, int V);
+bool build_twiddles(int L, int V, double *out_ri /* 2 * twiddle_entries(L, V) */);
 
 }  // namespace scint

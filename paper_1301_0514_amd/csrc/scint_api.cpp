@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -112,7 +113,9 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 
 // ------------------------------------------------------------ device caches
 struct DeviceCache {
-    std::map<std::pair<int, int>, void *> twiddles;  // (L, dtype) -> table
+    std::map<std::tuple<int, int, int>, void *> twiddles;  // (L, variant, dtype) -> table
+    std::map<std::pair<int, int>, int> variant;             // (L, dtype) -> plan variant in use
+    std::map<std::pair<int, int>, std::vector<float>> variant_ms;  // tuner timings
     // (N, dtype, radius bits...) -> n_r contiguous disk spectra
     std::map<std::pair<std::pair<int, int>, std::vector<uint64_t>>, void *> disks;
     std::map<hipStream_t, std::pair<void *, size_t>> workspace;
@@ -128,21 +131,21 @@ int current_device(int *dev) {
     return PS_OK;
 }
 
-// Twiddle table of the length-L plan in the working precision.
-int get_twiddles(int L, int dtype, const void **out) {
+// Twiddle table of plan (L, V) in the working precision.
+int get_twiddles(int L, int V, int dtype, const void **out) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
     std::lock_guard<std::mutex> lock(g_mutex);
     auto &dc = g_cache[dev];
-    auto key = std::make_pair(L, dtype);
+    auto key = std::make_tuple(L, V, dtype);
     auto it = dc.twiddles.find(key);
     if (it != dc.twiddles.end()) {
         *out = it->second;
         return PS_OK;
     }
-    const int n = twiddle_entries(L);
+    const int n = twiddle_entries(L, V);
     std::vector<double> ri(2 * (size_t)std::max(n, 1));
-    if (n > 0 && !build_twiddles(L, ri.data())) return fail(PS_E_SIZE, "no FFT plan for this size");
+    if (n > 0 && !build_twiddles(L, V, ri.data())) return fail(PS_E_SIZE, "no FFT plan for this size");
     const size_t bytes = 2 * real_bytes(dtype) * (size_t)std::max(n, 1);
     void *d = nullptr;
     if (hipMalloc(&d, bytes) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of twiddle table failed");
@@ -366,18 +369,120 @@ SCINT_PROG_NAME(ProgVjpY)
 SCINT_PROG_NAME(ProgVjpX)
 #undef SCINT_PROG_NAME
 
+int plan_variant(int N, int dtype, int *V);
+
 template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_ops, hipStream_t stream) {
+    int V = 0;
+    if (int rc = plan_variant(N, dtype, &V)) return rc;
     const void *tw = nullptr;
-    if (int rc = get_twiddles(N, dtype, &tw)) return rc;
+    if (int rc = get_twiddles(N, V, dtype, &tw)) return rc;
     hipEvent_t t0 = nullptr;
     const bool timed = timing_begin(stream, &t0);
-    hipError_t e = dtype == PS_F64 ? launch_row<double, Tag>(N, p, tw, stream)
-                                   : launch_row<float, Tag>(N, p, tw, stream);
+    hipError_t e = dtype == PS_F64 ? launch_row<double, Tag>(N, V, p, tw, stream)
+                                   : launch_row<float, Tag>(N, V, p, tw, stream);
     if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("row pass launch: ") + hipGetErrorString(e));
     if (timed)
         timing_end(stream, t0,
                    std::string("row_") + prog_name<Tag>() + "_" + real_name(dtype) + "_N" + std::to_string(N),
                    row_bytes(p, n_ops, dtype), row_flops(p, n_ops));
+    return PS_OK;
+}
+
+// ------------------------------------------------------------ plan tuner
+// The large FP32 sizes have several compiled Stockham plans (fft_plan.hpp).
+// On the first FP32 call of such a size on a device, each plan is timed on a
+// propagation row pass (FFT, chirp multiply, inverse FFT, |.|^2, 4 iterations)
+// over 1024 rows of scratch data, on a private stream; the fastest is kept,
+// unless it beats plan 0 by less than 3% (stable choices across runs).
+// SCINT_PLAN_VARIANT=<v> in the environment, or ps_set_plan_variant, pins it.
+int tune_plan(int N, std::vector<float> *ms_out, int *best) {
+    const int nv = plan_variants(N);
+    const int rows = 1024, iters = 4;
+    const size_t cb = (size_t)rows * N * 8;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, cb + (size_t)rows * N * 4 + (size_t)iters * N * 8 + 1024) != hipSuccess)
+        return fail(PS_E_ALLOC, "hipMalloc of tuner scratch failed");
+    char *S = static_cast<char *>(buf);
+    char *Sr = S + cb;
+    char *H = Sr + (size_t)rows * N * 4;
+    hipStream_t s = nullptr;
+    int rc = PS_OK;
+    if (hipStreamCreate(&s) != hipSuccess) rc = fail(PS_E_DEVICE, "hipStreamCreate for the tuner failed");
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!rc && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess))
+        rc = fail(PS_E_DEVICE, "hipEventCreate for the tuner failed");
+    if (!rc && hipMemsetAsync(buf, 0, cb + (size_t)rows * N * 4 + (size_t)iters * N * 8, s) != hipSuccess)
+        rc = fail(PS_E_DEVICE, "tuner scratch clear failed");
+    ProgBuilder p(N, rows);
+    p.p.n_iter = iters;
+    p.op(ROP_LOOP)
+        .op(ROP_LOAD_C, S, 0, N)
+        .op(ROP_FFT_FWD)
+        .op(ROP_MUL_TAB, H, 0, 0, N)
+        .op(ROP_FFT_INV)
+        .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0)
+        .op(ROP_ENDLOOP)
+        .op(ROP_STORE_ACC, Sr, 0, N);
+    ms_out->assign(nv, 0.0f);
+    for (int v = 0; v < nv && !rc; ++v) {
+        const void *tw = nullptr;
+        if ((rc = get_twiddles(N, v, PS_F32, &tw))) break;
+        float best_ms = 1e30f;
+        for (int r = 0; r < 4 && !rc; ++r) {
+            (void)hipEventRecord(a, s);
+            hipError_t e = launch_row<float, ProgPropIntensityTag>(N, v, p.p, tw, s);
+            (void)hipEventRecord(b, s);
+            if (e != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                rc = fail(PS_E_DEVICE, "tuner launch failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (r > 0) best_ms = std::min(best_ms, ms);  // first launch warms up
+        }
+        (*ms_out)[v] = best_ms;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(buf);
+    if (rc) return rc;
+    int bv = 0;
+    for (int v = 1; v < nv; ++v)
+        if ((*ms_out)[v] < (*ms_out)[bv]) bv = v;
+    if (bv != 0 && (*ms_out)[bv] > 0.97f * (*ms_out)[0]) bv = 0;
+    *best = bv;
+    return PS_OK;
+}
+
+int plan_variant(int N, int dtype, int *V) {
+    *V = 0;
+    if (dtype == PS_F64 || plan_variants(N) == 1) return PS_OK;
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    const auto key = std::make_pair(N, dtype);
+    {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        auto &dc = g_cache[dev];
+        auto it = dc.variant.find(key);
+        if (it != dc.variant.end()) {
+            *V = it->second;
+            return PS_OK;
+        }
+    }
+    int chosen = -1;
+    if (const char *env = std::getenv("SCINT_PLAN_VARIANT")) {
+        const int v = std::atoi(env);
+        if (v >= 0 && v < plan_variants(N)) chosen = v;
+    }
+    std::vector<float> ms;
+    if (chosen < 0)
+        if (int rc = tune_plan(N, &ms, &chosen)) return rc;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto &dc = g_cache[dev];
+    dc.variant[key] = chosen;
+    if (!ms.empty()) dc.variant_ms[key] = ms;
+    *V = chosen;
     return PS_OK;
 }
 
@@ -453,6 +558,48 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
 extern "C" {
 
 int ps_version(void) { return 10000; }
+
+int ps_num_plan_variants(int N, int dtype) {
+    if (dtype == PS_F64) return supported_f64(N) ? 1 : 0;
+    if (dtype == PS_F32) return supported_f32(N) ? plan_variants(N) : 0;
+    return 0;
+}
+
+int ps_plan_variant(int N, int dtype, int *variant_out, float *ms_out) {
+    g_last_error.clear();
+    if (int rc = check_common(N, dtype, 1)) return rc;
+    if (!variant_out) return fail(PS_E_NULL, "variant_out is NULL");
+    int V = 0;
+    if (int rc = plan_variant(N, dtype, &V)) return rc;
+    *variant_out = V;
+    if (ms_out) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lock(g_mutex);
+        auto &dc = g_cache[dev];
+        auto it = dc.variant_ms.find(std::make_pair(N, dtype));
+        const int nv = ps_num_plan_variants(N, dtype);
+        for (int v = 0; v < nv; ++v)
+            ms_out[v] = (it != dc.variant_ms.end() && v < (int)it->second.size()) ? it->second[v] : -1.0f;
+    }
+    return PS_OK;
+}
+
+int ps_set_plan_variant(int N, int dtype, int variant) {
+    g_last_error.clear();
+    if (int rc = check_common(N, dtype, 1)) return rc;
+    if (variant < -1 || variant >= ps_num_plan_variants(N, dtype))
+        return fail(PS_E_PARAM, "plan variant out of range");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto &dc = g_cache[dev];
+    if (variant < 0)
+        dc.variant.erase(std::make_pair(N, dtype));
+    else
+        dc.variant[std::make_pair(N, dtype)] = variant;
+    return PS_OK;
+}
 
 int ps_timing_enable(int on) {
     timing_drain();

@@ -43,8 +43,8 @@ static void root_ld(long long m, long long M, long double &c, long double &s) {
     s = -sign_s * ss;  // forward transform: exp(-i angle)
 }
 
-template <int L> static void fill(double *out) {
-    using P = Plan<L>;
+template <int L, int V> static void fill(double *out) {
+    using P = Plan<L, V>;
     long long ns = 1;
     size_t idx = 0;
     for (int st = 0; st < P::NS; ++st) {
@@ -63,10 +63,15 @@ template <int L> static void fill(double *out) {
     }
 }
 
-int twiddle_entries(int L) {
+int twiddle_entries(int L, int V) {
+#define SCINT_VCASE(LL, VV) \
+    if (L == LL && V == VV) return twiddle_count<LL, VV>();
+    SCINT_VARIANTS_F32(SCINT_VCASE)
+#undef SCINT_VCASE
+    if (V != 0) return 0;
 #define SCINT_CASE(LL) \
     case LL:           \
-        return twiddle_count<LL>();
+        return twiddle_count<LL, 0>();
     switch (L) {
         SCINT_SIZES_F32(SCINT_CASE)
     default:
@@ -75,10 +80,18 @@ int twiddle_entries(int L) {
 #undef SCINT_CASE
 }
 
-bool build_twiddles(int L, double *out) {
-#define SCINT_CASE(LL)  \
-    case LL:            \
-        fill<LL>(out);  \
+bool build_twiddles(int L, int V, double *out) {
+#define SCINT_VCASE(LL, VV)     \
+    if (L == LL && V == VV) {   \
+        fill<LL, VV>(out);      \
+        return true;            \
+    }
+    SCINT_VARIANTS_F32(SCINT_VCASE)
+#undef SCINT_VCASE
+    if (V != 0) return false;
+#define SCINT_CASE(LL)     \
+    case LL:               \
+        fill<LL, 0>(out);  \
         return true;
     switch (L) {
         SCINT_SIZES_F32(SCINT_CASE)

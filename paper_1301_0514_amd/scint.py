@@ -46,6 +46,9 @@ SIGNATURES = {
     "ps_last_warning": (ctypes.c_char_p, []),
     "ps_release_cache": (_c_int, []),
     "ps_version": (_c_int, []),
+    "ps_num_plan_variants": (_c_int, [_c_int, _c_int]),
+    "ps_plan_variant": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_float)]),
+    "ps_set_plan_variant": (_c_int, [_c_int, _c_int, _c_int]),
     "ps_timing_enable": (_c_int, [_c_int]),
     "ps_timing_count": (_c_int, []),
     "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp,
@@ -143,6 +146,25 @@ def release_cache() -> None:
 
 def version() -> int:
     return load_library().ps_version()
+
+
+def num_plan_variants(N: int, dtype: torch.dtype = torch.float32) -> int:
+    return load_library().ps_num_plan_variants(int(N), _dtype_code(dtype))
+
+
+def plan_variant(N: int, dtype: torch.dtype = torch.float32):
+    """(plan in use, tuner times in ms per plan or -1) -- tunes N now if needed."""
+    lib = load_library()
+    nv = max(1, lib.ps_num_plan_variants(int(N), _dtype_code(dtype)))
+    v = _c_int()
+    ms = (ctypes.c_float * nv)()
+    _check("ps_plan_variant", lib.ps_plan_variant(int(N), _dtype_code(dtype), ctypes.byref(v), ms))
+    return v.value, [ms[i] for i in range(nv)]
+
+
+def set_plan_variant(N: int, variant: int, dtype: torch.dtype = torch.float32) -> None:
+    """Pin FFT plan `variant` for size N (-1: back to the tuner's choice)."""
+    _check("ps_set_plan_variant", load_library().ps_set_plan_variant(int(N), _dtype_code(dtype), int(variant)))
 
 
 def timing_enable(on: bool = True) -> None:

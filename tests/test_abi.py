@@ -105,3 +105,20 @@ def test_warning_for_undersampled_screen(lib):
     # message channel exists and is empty after a clean validation failure
     assert lib.ps_generate(256, 1.0, 4.0, 11 / 3, 1, 0, 1, 0, None, None) == -1
     assert lib.ps_last_warning() == b""
+
+
+def test_plan_variant_queries(lib):
+    assert lib.ps_num_plan_variants(8192, 0) == 3
+    assert lib.ps_num_plan_variants(8192, 1) == 1
+    assert lib.ps_num_plan_variants(256, 0) == 1
+    assert lib.ps_num_plan_variants(257, 0) == 0
+    # out-of-range variants are rejected before any device call
+    assert lib.ps_set_plan_variant(8192, 0, 3) == -3
+    assert lib.ps_set_plan_variant(8192, 0, -2) == -3
+    assert lib.ps_set_plan_variant(257, 0, 0) == -2
+
+
+def test_alignment_rejected(lib):
+    assert lib.ps_generate(256, 1.0, 4.0, 11 / 3, 1, 0, 1, 0, _vp((1 << 20) + 4), None) == -3
+    assert lib.fresnel_propagate(256, 1.0, 1.0, 1.0, _vp(1 << 20), 1.0, 1, 0, _vp((1 << 30) + 8), None) == -3
+    assert b"aligned" in lib.ps_last_error()

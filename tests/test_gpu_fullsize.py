@@ -227,3 +227,28 @@ def test_grad_fp64_256_finite_differences(S):
     Lp = loss_of(S.ps_generate(N, 1.0, R * np.exp(h), beta, 1, 0, 1, dtype=f64))
     Lm = loss_of(S.ps_generate(N, 1.0, R * np.exp(-h), beta, 1, 0, 1, dtype=f64))
     assert (Lp - Lm) / (2 * h) == pytest.approx((2 - beta) / 2 * dots[0], rel=1e-6)
+
+
+# ------------------------------------------------------------ every FFT plan variant
+@pytest.mark.parametrize("N", [2048, 4096, 8192, 10000, 16384])
+def test_every_plan_variant_vs_oracle(S, oracle, N):
+    """Each compiled Stockham plan of the large sizes, pinned in turn, against
+    the FP64 oracle (screen + propagation, R_diff = 30 px, R_F = 100 px)."""
+    rho, R, lam = 100.0, 30.0, 5e-7
+    z = 2 * np.pi * rho ** 2 / lam
+    I_ref = oracle.propagate(oracle.screen(N, R, 11 / 3, 2, 0), rho)
+    nv = S.num_plan_variants(N)
+    assert nv >= 2
+    try:
+        for v in range(nv):
+            S.set_plan_variant(N, v)
+            assert S.plan_variant(N)[0] == v
+            I = host(S.ps_screen_fresnel(N, 1.0, R, 11 / 3, 2, lam, z))[0]
+            e_rms, e_max = errs(I, I_ref)
+            print("N=%d plan %d e_rms=%.2e e_max=%.2e" % (N, v, e_rms, e_max))
+            assert e_rms < F32_RMS and e_max < F32_MAX
+    finally:
+        S.set_plan_variant(N, -1)
+    v, ms = S.plan_variant(N)
+    print("N=%d tuner picked plan %d, times %s ms" % (N, v, ms))
+    assert 0 <= v < nv and all(t > 0 for t in ms)
