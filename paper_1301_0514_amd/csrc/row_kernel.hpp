@@ -183,6 +183,9 @@ template <class Ops> constexpr int find_endloop(int i) {
     return Ops::n;
 }
 
+// two-lane vector of Real, the unit of the streaming complex loads and stores
+template <typename Real> using Real2 = Real __attribute__((ext_vector_type(2)));
+
 template <typename Real, int L, int V> struct RowState {
     static constexpr int E = Plan<L, V>::E;
     cpx<Real> v[E];
@@ -201,23 +204,30 @@ template <typename Real, int L, int V, int CODE>
 __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &op) {
     constexpr int E = Plan<L, V>::E, T = Plan<L, V>::T;
     auto &v = st.v;
+    // Rows past the end of the batch (st.valid false) are given batch 0,
+    // row 0, so their loads stay inside the operands and need no predicate
+    // (a per-element guard serialises the loads); only stores are guarded.
     const bool valid = st.valid;
     const int64_t off = (int64_t)st.batch * op.batch_stride + (int64_t)st.it * op.iter_stride +
                         (int64_t)st.row * op.row_stride + st.t;
     const double s = (op.flags & RF_ITER_SCALE) ? st.prog->scale[st.it] : op.param;
     if constexpr (CODE == ROP_LOAD_C) {
+        // complex rows are read once per pass: streaming (nontemporal) loads
         const cpx<Real> *src = static_cast<const cpx<Real> *>(op.ptr) + off;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = valid ? src[m * T] : cpx<Real>{(Real)0, (Real)0};
+        for (int m = 0; m < E; ++m) {
+            const Real2<Real> x = __builtin_nontemporal_load(reinterpret_cast<const Real2<Real> *>(src + m * T));
+            v[m] = {x.x, x.y};
+        }
     } else if constexpr (CODE == ROP_LOAD_R) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = {valid ? src[m * T] : (Real)0, (Real)0};
+        for (int m = 0; m < E; ++m) v[m] = {src[m * T], (Real)0};
     } else if constexpr (CODE == ROP_LOAD_PHASE) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
         const double sturn = s * (0.5 / kPi);
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)(valid ? src[m * T] : (Real)0));
+        for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)src[m * T]);
     } else if constexpr (CODE == ROP_NOISE) {
         const uint32_t r = (uint32_t)st.prog->r0 + (uint32_t)st.batch;
 #pragma unroll
@@ -225,7 +235,7 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
     } else if constexpr (CODE == ROP_KEEP_R) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
 #pragma unroll
-        for (int m = 0; m < E; ++m) st.keep[m] = valid ? src[m * T] : (Real)0;
+        for (int m = 0; m < E; ++m) st.keep[m] = src[m * T];
     } else if constexpr (CODE == ROP_EXP_KEEP) {
         const double sturn = s * (0.5 / kPi);
 #pragma unroll
@@ -256,7 +266,7 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         const Real *src = static_cast<const Real *>(op.ptr) + off;
         const Real sc = (Real)op.param;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = cscale(v[m], sc * (valid ? src[m * T] : (Real)0));
+        for (int m = 0; m < E; ++m) v[m] = cscale(v[m], sc * src[m * T]);
     } else if constexpr (CODE == ROP_SQRT2RE) {
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = {sqrt2_of<Real>() * v[m].re, (Real)0};
@@ -266,9 +276,15 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)v[m].re);
     } else if constexpr (CODE == ROP_STORE_C) {
         if (valid && op.ptr != nullptr) {
+            // written once, read by a later pass: streaming (nontemporal) stores
             cpx<Real> *dst = static_cast<cpx<Real> *>(const_cast<void *>(op.ptr)) + off;
 #pragma unroll
-            for (int m = 0; m < E; ++m) dst[m * T] = v[m];
+            for (int m = 0; m < E; ++m) {
+                Real2<Real> x;
+                x.x = v[m].re;
+                x.y = v[m].im;
+                __builtin_nontemporal_store(x, reinterpret_cast<Real2<Real> *>(dst + m * T));
+            }
         }
     } else if constexpr (CODE == ROP_STORE_R) {
         if (valid && op.ptr != nullptr) {
@@ -304,7 +320,7 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         const Real sc = (Real)s;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
-            const cpx<Real> u = expi_turns<Real>(sturn * (double)(valid ? src[m * T] : (Real)0));
+            const cpx<Real> u = expi_turns<Real>(sturn * (double)src[m * T]);
             v[m] = {sc * (v[m].im * u.re - v[m].re * u.im), (Real)0};  // s Im(v conj(u))
         }
     } else if constexpr (CODE == ROP_DOT_R) {
@@ -313,7 +329,7 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         const Real *src = static_cast<const Real *>(op.ptr) + off;
         double part = 0.0;
 #pragma unroll
-        for (int m = 0; m < E; ++m) part += (double)(valid ? src[m * T] : (Real)0) * (double)v[m].re;
+        for (int m = 0; m < E; ++m) part += (double)src[m * T] * (double)v[m].re;
         double *red = st.red;
         __syncthreads();
         red[st.tid] = part;

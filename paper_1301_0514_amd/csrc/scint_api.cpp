@@ -397,7 +397,9 @@ template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_op
 // SCINT_PLAN_VARIANT=<v> in the environment, or ps_set_plan_variant, pins it.
 int tune_plan(int N, std::vector<float> *ms_out, int *best) {
     const int nv = plan_variants(N);
-    const int rows = 1024, iters = 4;
+    // about 2^24 points per launch (several waves of workgroups at every
+    // size), four wavelength iterations
+    const int rows = std::max(1024, (1 << 24) / N), iters = 4;
     const size_t cb = (size_t)rows * N * 8;
     void *buf = nullptr;
     if (hipMalloc(&buf, cb + (size_t)rows * N * 4 + (size_t)iters * N * 8 + 1024) != hipSuccess)
@@ -416,21 +418,22 @@ int tune_plan(int N, std::vector<float> *ms_out, int *best) {
     ProgBuilder p(N, rows);
     p.p.n_iter = iters;
     p.op(ROP_LOOP)
-        .op(ROP_LOAD_C, S, 0, N)
+        .op(ROP_LOAD_C, S, (int64_t)N * N, N)
         .op(ROP_FFT_FWD)
         .op(ROP_MUL_TAB, H, 0, 0, N)
         .op(ROP_FFT_INV)
         .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0)
         .op(ROP_ENDLOOP)
-        .op(ROP_STORE_ACC, Sr, 0, N);
-    ms_out->assign(nv, 0.0f);
-    for (int v = 0; v < nv && !rc; ++v) {
-        const void *tw = nullptr;
-        if ((rc = get_twiddles(N, v, PS_F32, &tw))) break;
-        float best_ms = 1e30f;
-        for (int r = 0; r < 4 && !rc; ++r) {
+        .op(ROP_STORE_ACC, Sr, (int64_t)N * N, N);  // row g at g N: inside the scratch
+    // rounds over all variants in turn (so drift affects them alike); the
+    // first round warms up, then the minimum over the timed rounds counts
+    ms_out->assign(nv, 1e30f);
+    std::vector<const void *> tws(nv, nullptr);
+    for (int v = 0; v < nv && !rc; ++v) rc = get_twiddles(N, v, PS_F32, &tws[v]);
+    for (int r = 0; r < 6 && !rc; ++r) {
+        for (int v = 0; v < nv && !rc; ++v) {
             (void)hipEventRecord(a, s);
-            hipError_t e = launch_row<float, ProgPropIntensityTag>(N, v, p.p, tw, s);
+            hipError_t e = launch_row<float, ProgPropIntensityTag>(N, v, p.p, tws[v], s);
             (void)hipEventRecord(b, s);
             if (e != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
                 rc = fail(PS_E_DEVICE, "tuner launch failed");
@@ -438,9 +441,8 @@ int tune_plan(int N, std::vector<float> *ms_out, int *best) {
             }
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, a, b);
-            if (r > 0) best_ms = std::min(best_ms, ms);  // first launch warms up
+            if (r > 0) (*ms_out)[v] = std::min((*ms_out)[v], ms);
         }
-        (*ms_out)[v] = best_ms;
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
