@@ -68,6 +68,10 @@ def _load():
                 "oracle_smear_direct": (None, [c_int, dp, c_dbl, dp]),
                 "oracle_disk_count": (c_dbl, [c_int, c_dbl]),
                 "oracle_modulation_index": (c_dbl, [c_int, dp]),
+                "oracle_sf_window": (None, [c_int, c_dbl, dp]),
+                "oracle_fresnel_aperture": (None, [c_int, c_dbl, c_dbl, c_dbl, dp, dp]),
+                "oracle_fresnel_aperture_direct": (None, [c_int, c_dbl, c_dbl, c_dbl, dp, dp]),
+                "oracle_modulation_index_region": (c_dbl, [c_int, dp, c_int, c_int, c_int, c_int, dp]),
                 "oracle_propagate_vjp": (None, [c_int, c_dbl, c_dbl, dp, dp, dp]),
                 "oracle_propagate_adjoint_field": (None, [c_int, c_dbl, dp, dp]),
                 "oracle_propagate_field": (None, [c_int, c_dbl, dp, dp]),
@@ -213,6 +217,45 @@ def fresnel_onefft(phi, rho: float) -> np.ndarray:
     out = np.zeros((N, N), dtype=np.float64)
     _load().oracle_fresnel_onefft(N, rho, _dp(phi), _dp(out))
     return out
+
+
+def sf_window(N: int, margin_px: float) -> np.ndarray:
+    """The smoothing window SF at the N pixel centres for a margin of
+    margin_px pixels on each border (Sect. 3.2.1); margin 0 = no window."""
+    out = np.zeros(N, dtype=np.float64)
+    _load().oracle_sf_window(N, margin_px, _dp(out))
+    return out
+
+
+def fresnel_aperture(phi, rho: float, s: float = 1.0, margin_rf: float = 10.0) -> np.ndarray:
+    """Aperture mode (Sect. 3.2, Eqs. intens and Gxy, with the window of
+    Sect. 3.2.1): |FT[SF SF G]|^2 / (2 pi rho^2)^2 on the observer grid of
+    pixel 2 pi rho^2 / N, centred (observer pixel N/2 faces screen pixel N/2).
+    margin_rf = L_m / R_F (the paper uses 10; 0 = no window)."""
+    phi = _f64(phi)
+    N = phi.shape[0]
+    out = np.zeros((N, N), dtype=np.float64)
+    _load().oracle_fresnel_aperture(N, rho, s, margin_rf, _dp(phi), _dp(out))
+    return out
+
+
+def fresnel_aperture_direct(phi, rho: float, s: float = 1.0, margin_rf: float = 10.0) -> np.ndarray:
+    """The aperture-mode intensity from the Fresnel sum (Eq. hxy) at each
+    observer point, O(N^4): for small N only."""
+    phi = _f64(phi)
+    N = phi.shape[0]
+    out = np.zeros((N, N), dtype=np.float64)
+    _load().oracle_fresnel_aperture_direct(N, rho, s, margin_rf, _dp(phi), _dp(out))
+    return out
+
+
+def modulation_index_region(I, x0: int, y0: int, w: int, h: int):
+    """(m, mean) over the w x h rectangle starting at pixel (x0, y0): the
+    statistics inside a fiducial zone (Sect. 3.2.1, Sect. 4)."""
+    I = _f64(I)
+    mean = ctypes.c_double(0.0)
+    m = _load().oracle_modulation_index_region(I.shape[0], _dp(I), x0, y0, w, h, ctypes.byref(mean))
+    return m, mean.value
 
 
 def propagate_field(field, rho: float) -> np.ndarray:
