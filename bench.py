@@ -335,6 +335,21 @@ def main(argv=None) -> int:
             log("%d^2 single lambda: %.3f ms" % (c.N, tp))
             del out_t
 
+        # aperture mode (one-FFT numerics with the window), 8192^2 at the
+        # conjugate relation N delta^2 = lambda z, on the bench's first screen
+        Na = 8192
+        phia = phi[:1] if phi.shape[-1] == Na else torch.zeros((1, Na, Na), dtype=torch.float32, device=dev)
+        lam_a = 2.162e-6
+        Ia = torch.empty_like(phia)
+
+        def aperture():
+            scint.fresnel_aperture(phia, 1.0, lam_a, Na / lam_a, margin_rf=10.0, out=Ia)
+
+        ta = timed(aperture, 3)
+        sec["aperture_8192_fresnel"] = {"ms_per_call": ta, "pt_per_s": Na ** 2 / (ta / 1e3)}
+        log("aperture mode 8192^2: %.3f ms" % ta)
+        del Ia
+
         # forward + adjoint, 16 x 2048^2
         g = presets.GRAD_2048
         nr = presets.GRAD_N_REAL

@@ -174,6 +174,47 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
                           void *grad_phi_out, double *phi_dot_grad_out, void *hip_stream);
 
 /*
+ * fresnel_aperture -- the paper's own numerics for a bounded screen
+ * (Sect. 3.2, Eqs. intens and Gxy, with the screen regularisation of
+ * Sect. 3.2.1): one 2-D DFT of the windowed, chirped screen read out on the
+ * observer grid.  For each of the n screens phi (radians, scaled by s):
+ *   G[y][x] = SF(x) SF(y) exp(i (s phi[y][x] + ((x - N/2)^2 + (y - N/2)^2) / (2 rho^2))),
+ *   I[my][mx] = |DFT[G](ky, kx)|^2 / (2 pi rho^2)^2,  k = m - N/2 (mod N),
+ * with rho = R_F / delta = sqrt(lambda z / 2 pi) / delta.  Screen pixel j
+ * has the coordinate (j - N/2) delta; observer pixel m has the coordinate
+ * (m - N/2) lambda z / (N delta): the observer pixel is lambda z / (N delta)
+ * and observer pixel N/2 faces screen pixel N/2.  SF is the raised-sine
+ * window of the paper over a margin L_m = margin_rf R_F at each border
+ * (the paper uses margin_rf = 10; 0 = no window), evaluated at the pixel
+ * centres, (j + 1/2) delta from the border.  The 2-D prefactor 1/(2 pi R_F^2)
+ * is applied to the field, so an unbounded uniform screen gives I = 1.  At
+ * N delta^2 = lambda z (Sect. 3.4) and margin_rf = 0 the result equals
+ * fresnel_propagate pixel by pixel.
+ *   phi        device [n][N][N] real (input, not modified)
+ *   margin_rf  L_m / R_F >= 0, with 2 L_m <= N delta (else PS_E_PARAM)
+ *   I_out      device [n][N][N] real; must not overlap phi (PS_E_ALIAS)
+ * N delta^2 > lambda z is rejected (PS_E_PARAM): the chirp would be sampled
+ * below two points per period at the screen border (the aliasing criterion
+ * of Sect. 3.2.2) and would fold light from there onto the observer grid.
+ */
+int fresnel_aperture(int N, double delta, double lambda, double z, const void *phi,
+                     double phase_scale, double margin_rf, int n, int dtype, void *I_out,
+                     void *hip_stream);
+
+/*
+ * ps_aperture_geometry -- the observer grid of fresnel_aperture and its
+ * fiducial zone (Sect. 3.2.1): observer_pixel = lambda z / (N delta) (length
+ * unit of delta), and fiducial_margin = ceil((R_ref / 2 + r_s) /
+ * observer_pixel) pixels to exclude at each border, R_ref = lambda z / r_diff
+ * (= 2 pi R_F^2 / R_diff, the refractive scale) and r_s the projected source
+ * radius (0 for a point source; the extended-source zone adds R_s).  Host
+ * arithmetic only.  A warning is set when the zone is empty
+ * (2 fiducial_margin >= N); fiducial_margin is capped at N.
+ */
+int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_diff,
+                         double r_s, double *observer_pixel, int *fiducial_margin);
+
+/*
  * ps_modulation_index -- m = sigma_I / mean(I) per pattern (Sect. 4),
  * population sigma over all N^2 pixels, FP64 accumulation in a fixed order
  * (bitwise reproducible).
@@ -182,6 +223,17 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
  */
 int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out,
                         double *mean_out, void *hip_stream);
+
+/*
+ * ps_modulation_index_region -- m and the mean as ps_modulation_index, over
+ * the w x h rectangle whose first pixel is (x0, y0) in each pattern: the
+ * statistics inside a fiducial zone (Sect. 3.2.1, Sect. 4).  The rectangle
+ * must be non-empty and inside the image (PS_E_PARAM).
+ *   I       device [n][N][N] real
+ *   m_out   host array of n doubles;  mean_out optional host array of n doubles
+ */
+int ps_modulation_index_region(int N, const void *I, int n, int x0, int y0, int w, int h,
+                               int dtype, double *m_out, double *mean_out, void *hip_stream);
 
 /*
  * ps_l2_loss -- L = sum_m (I - I_target)^2 per pattern and its gradient

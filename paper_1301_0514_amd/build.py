@@ -24,7 +24,8 @@ LIB = os.path.join(LIBDIR, "libscint.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 PROGRAMS = ["ProgNoise", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgPropIntensity",
-            "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX"]
+            "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX",
+            "ProgApertureX", "ProgAbs2"]
 
 # gfx950 only; packed FP32 instructions are disabled (the compiler would
 # otherwise form them from float code).

@@ -26,6 +26,17 @@ hipError_t launch_disk_image(void *img, int N, double r2, double value, bool f64
 hipError_t launch_block_sums(const void *x, int64_t n_per_batch, int nbatch, const double *center,
                              int power, int nblk, bool f64, double *partials, hipStream_t stream);
 
+// As launch_block_sums over a w x h region of each batch member: rows of
+// w elements, row_stride apart, starting at x + b * batch_stride.
+hipError_t launch_region_sums(const void *x, int64_t batch_stride, int64_t w, int64_t h, int64_t row_stride,
+                              int nbatch, const double *center, int power, int nblk, bool f64, double *partials,
+                              hipStream_t stream);
+
+// tab[j] = SF(j + 1/2) exp(i (2 pi a (j - N/2)^2 + pi j)), j < N, with SF the
+// raised-sine window over Lm pixels at each border (Lm = 0: SF = 1); the
+// phase is formed and reduced in FP64 turns, the sine/cosine taken in FP64.
+hipError_t launch_aperture_table(void *tab, int N, double a, double Lm, bool f64, hipStream_t stream);
+
 // out[b] = scale * sum_blk partials[b * nblk + blk], fixed-order tree.
 hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,
                                 hipStream_t stream);

@@ -166,6 +166,42 @@ hipError_t launch_chirp_tables(void *tab, int N, const double *a, int n, double 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- aperture
+// A[j] = SF(j + 1/2) exp(i ((j - N/2)^2 / (2 rho^2) + pi j)) in FP64, rounded
+// once.  The phase is formed in turns, (j - N/2)^2 exactly times
+// 1/(4 pi rho^2), plus j/2, and reduced to [-1/2, 1/2] before sincospi.  The
+// window is the raised sine over Lm pixels at each border (Lm = 0: none).
+template <typename Real>
+__global__ __launch_bounds__(256) void aperture_table_kernel(cpx<Real> *tab, int N, double a, double Lm) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const double d = (double)(j - N / 2);
+    const double turns = a * (d * d) + 0.5 * (double)(j & 1);
+    const double f = turns - rint(turns);
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    const double x = (double)j + 0.5;
+    double w = 1.0;
+    if (Lm > 0.0) {
+        if (x <= Lm)
+            w = 0.5 * (1.0 - cospi(x / Lm));
+        else if (x >= (double)N - Lm)
+            w = 0.5 * (1.0 + cospi((x - (double)N + Lm) / Lm));
+    }
+    tab[j] = {(Real)(w * c), (Real)(w * s)};
+}
+
+hipError_t launch_aperture_table(void *tab, int N, double a, double Lm, bool f64, hipStream_t stream) {
+    dim3 grid((N + 255) / 256);
+    if (f64)
+        hipLaunchKernelGGL((aperture_table_kernel<double>), grid, dim3(256), 0, stream,
+                           static_cast<cpx<double> *>(tab), N, a, Lm);
+    else
+        hipLaunchKernelGGL((aperture_table_kernel<float>), grid, dim3(256), 0, stream,
+                           static_cast<cpx<float> *>(tab), N, a, Lm);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- disk
 template <typename Real>
 __global__ __launch_bounds__(256) void disk_kernel(Real *img, int N, double r2, double value) {
@@ -200,32 +236,48 @@ __device__ __forceinline__ double block_tree_sum(double v, double *red) {
     return red[0];
 }
 
+// Partial sums of (x - center)^power over a w-wide region of each batch
+// member: element i of the region is x[b * batch_stride + (i / w) *
+// row_stride + i % w]; a contiguous run when w == row_stride.
 template <typename Real>
-__global__ __launch_bounds__(256) void block_sums_kernel(const Real *__restrict__ x, int64_t n, const double *center,
+__global__ __launch_bounds__(256) void block_sums_kernel(const Real *__restrict__ x, int64_t n, int64_t batch_stride,
+                                                         int64_t w, int64_t row_stride, const double *center,
                                                          int power, double *partials) {
     __shared__ double red[256];
     const int b = blockIdx.y, nblk = gridDim.x;
-    const Real *xb = x + (int64_t)b * n;
+    const Real *xb = x + (int64_t)b * batch_stride;
     const double c = center ? center[b] : 0.0;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
-        const double d = (double)xb[i] - c;
+        const int64_t e = (w == row_stride) ? i : (i / w) * row_stride + i % w;
+        const double d = (double)xb[e] - c;
         acc += (power == 2) ? d * d : d;
     }
     const double tot = block_tree_sum(acc, red);
     if (threadIdx.x == 0) partials[(int64_t)b * nblk + blockIdx.x] = tot;
 }
 
-hipError_t launch_block_sums(const void *x, int64_t n_per_batch, int nbatch, const double *center, int power,
-                             int nblk, bool f64, double *partials, hipStream_t stream) {
+hipError_t launch_region_sums(const void *x, int64_t batch_stride, int64_t w, int64_t h, int64_t row_stride,
+                              int nbatch, const double *center, int power, int nblk, bool f64, double *partials,
+                              hipStream_t stream) {
     dim3 grid(nblk, nbatch);
+    const int64_t n = w * h;
+    // a full-width region (or a single row) is one contiguous run
+    const bool run = row_stride == w || h == 1;
+    const int64_t ww = run ? 1 : w, rs = run ? 1 : row_stride;
     if (f64)
         hipLaunchKernelGGL((block_sums_kernel<double>), grid, dim3(256), 0, stream, static_cast<const double *>(x),
-                           n_per_batch, center, power, partials);
+                           n, batch_stride, ww, rs, center, power, partials);
     else
-        hipLaunchKernelGGL((block_sums_kernel<float>), grid, dim3(256), 0, stream, static_cast<const float *>(x),
-                           n_per_batch, center, power, partials);
+        hipLaunchKernelGGL((block_sums_kernel<float>), grid, dim3(256), 0, stream, static_cast<const float *>(x), n,
+                           batch_stride, ww, rs, center, power, partials);
     return hipGetLastError();
+}
+
+hipError_t launch_block_sums(const void *x, int64_t n_per_batch, int nbatch, const double *center, int power,
+                             int nblk, bool f64, double *partials, hipStream_t stream) {
+    return launch_region_sums(x, n_per_batch, n_per_batch, 1, n_per_batch, nbatch, center, power, nblk, f64,
+                              partials, stream);
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(const double *partials, int nblk, double scale, double *out) {

@@ -274,6 +274,10 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         const double sturn = s * (0.5 / kPi);
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)v[m].re);
+    } else if constexpr (CODE == ROP_MUL_ROWTAB) {
+        const cpx<Real> a = static_cast<const cpx<Real> *>(op.ptr)[(int64_t)st.it * op.iter_stride + st.row];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cmul(v[m], a);
     } else if constexpr (CODE == ROP_STORE_C) {
         if (valid && op.ptr != nullptr) {
             // written once, read by a later pass: streaming (nontemporal) stores
@@ -411,5 +415,9 @@ using ProgVjpY = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_M
                         ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
 using ProgVjpX = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_GRAD_PHI, ROP_STORE_R,
                         ROP_DOT_R>;
+// aperture mode: windowed, chirped exp(i s phi) -> DFT along the row; then
+// DFT along the other axis and |.|^2
+using ProgApertureX = OpList<ROP_LOAD_PHASE, ROP_MUL_TAB, ROP_MUL_ROWTAB, ROP_FFT_FWD, ROP_STORE_C>;
+using ProgAbs2 = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_ACC_ABS2, ROP_STORE_ACC>;
 
 }  // namespace scint

@@ -19,6 +19,8 @@ struct ProgSmearMidTag;
 struct ProgInvReTag;
 struct ProgVjpYTag;
 struct ProgVjpXTag;
+struct ProgApertureXTag;
+struct ProgAbs2Tag;
 
 // Launches program Tag on total_rows rows of length L (the grid size N) with
 // plan variant V; tw is the device twiddle table of that plan in the same

@@ -40,6 +40,7 @@ enum RowOpCode : int32_t {
     ROP_DOT_R,       // ptr2[global row] = sum_e src[e] Re v   (double)
     ROP_LOOP,        // start of the repeated range
     ROP_ENDLOOP,     // end of the repeated range
+    ROP_MUL_ROWTAB,  // v *= tab[row]  (complex, one factor per row)
 };
 
 // Flag bits

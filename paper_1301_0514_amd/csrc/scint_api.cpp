@@ -341,7 +341,7 @@ double row_flops(const RowProgram &p, int n_ops) {
         case ROP_LOOP: in_loop = true; break;
         case ROP_ENDLOOP: in_loop = false; break;
         case ROP_FFT_FWD: case ROP_FFT_INV: f = 5.0 * log2n; break;
-        case ROP_MUL_TAB: f = 6.0; break;
+        case ROP_MUL_TAB: case ROP_MUL_ROWTAB: f = 6.0; break;
         case ROP_MUL_RTAB2D: case ROP_MUL_RLOAD: case ROP_DOT_R: f = 2.0; break;
         case ROP_ACC_ABS2: f = 5.0; break;
         case ROP_GRAD_PHI: f = 4.0; break;
@@ -367,6 +367,8 @@ SCINT_PROG_NAME(ProgSmearMid)
 SCINT_PROG_NAME(ProgInvRe)
 SCINT_PROG_NAME(ProgVjpY)
 SCINT_PROG_NAME(ProgVjpX)
+SCINT_PROG_NAME(ProgApertureX)
+SCINT_PROG_NAME(ProgAbs2)
 #undef SCINT_PROG_NAME
 
 int plan_variant(int N, int dtype, int *V);
@@ -834,6 +836,81 @@ int fresnel_propagate(int N, double delta, double lambda, double z, const void *
     return PS_OK;
 }
 
+int fresnel_aperture(int N, double delta, double lambda, double z, const void *phi, double phase_scale,
+                     double margin_rf, int n, int dtype, void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
+    if (int rc = check_aligned({phi, I_out})) return rc;
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    if (!(std::isfinite(margin_rf) && margin_rf >= 0.0)) return fail(PS_E_PARAM, "margin_rf must be finite and >= 0");
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const double two_pi_rho2 = 2.0 * kPiD * rho * rho;
+    if ((double)N > two_pi_rho2 * (1.0 + 1e-9))
+        return fail(PS_E_PARAM, "N delta^2 > lambda z: the Fresnel chirp is undersampled at the screen border");
+    const double Lm = margin_rf * rho;
+    if (2.0 * Lm > (double)N) return fail(PS_E_PARAM, "the window margins (2 margin_rf R_F) exceed the screen");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
+    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    const double norm = 1.0 / (two_pi_rho2 * two_pi_rho2);
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        void *A = base + c.take(tbytes);
+        HIP_TRY(launch_aperture_table(A, N, 1.0 / (4.0 * kPiD * rho * rho), Lm, dtype == PS_F64, stream));
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        // rows y: G = A[x] A[y] exp(i s phi), DFT along x
+        ProgBuilder a(N, (int64_t)nb * N);
+        a.op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
+            .op(ROP_MUL_TAB, A)
+            .op(ROP_MUL_ROWTAB, A)
+            .op(ROP_FFT_FWD)
+            .op(ROP_STORE_C, W1, nn(N), N);
+        if (int rc = run_row<ProgApertureXTag>(dtype, N, a.p, a.n, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
+        // rows kx: DFT along y, |.|^2 / (2 pi rho^2)^2 (transposed intensity in W1)
+        ProgBuilder d(N, (int64_t)nb * N);
+        d.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, norm)
+            .op(ROP_STORE_ACC, W1, nn(N), N);
+        if (int rc = run_row<ProgAbs2Tag>(dtype, N, d.p, d.n, stream)) return rc;
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
+    return PS_OK;
+}
+
+int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_diff, double r_s,
+                         double *observer_pixel, int *fiducial_margin) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (N < 2) return fail(PS_E_SIZE, "N must be >= 2");
+    if (!observer_pixel || !fiducial_margin) return fail(PS_E_NULL, "observer_pixel and fiducial_margin must be non-NULL");
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z) || !finite_pos(r_diff))
+        return fail(PS_E_PARAM, "delta, lambda, z and r_diff must be finite and > 0");
+    if (!(std::isfinite(r_s) && r_s >= 0.0)) return fail(PS_E_PARAM, "r_s must be finite and >= 0");
+    const double pix0 = lambda * z / ((double)N * delta);
+    const double r_ref = lambda * z / r_diff;  // 2 pi R_F^2 / R_diff
+    const double m = std::ceil((0.5 * r_ref + r_s) / pix0);
+    *observer_pixel = pix0;
+    *fiducial_margin = m > (double)N ? N : (int)m;
+    if (2.0 * m >= (double)N) g_last_warning = "the fiducial zone is empty at this geometry";
+    return PS_OK;
+}
+
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref, double lambda_ref,
                                const double *lambdas, const double *weights, int n_lambda, int n_real, int dtype,
                                void *I_out, void *hip_stream) {
@@ -1139,6 +1216,42 @@ int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out, d
     HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0 / (double)per, mean, stream));
     HIP_TRY(launch_block_sums(I, per, n, mean, 2, nblk, f64, part, stream));
     HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0 / (double)per, var, stream));
+    std::vector<double> hm(n), hv(n);
+    HIP_TRY(hipMemcpyAsync(hm.data(), mean, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(hv.data(), var, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (int b = 0; b < n; ++b) {
+        m_out[b] = std::sqrt(hv[b]) / hm[b];
+        if (mean_out) mean_out[b] = hm[b];
+    }
+    return PS_OK;
+}
+
+int ps_modulation_index_region(int N, const void *I, int n, int x0, int y0, int w, int h, int dtype, double *m_out,
+                               double *mean_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!I || !m_out) return fail(PS_E_NULL, "I and m_out must be non-NULL");
+    if (int rc = check_aligned({I})) return rc;
+    if (x0 < 0 || y0 < 0 || w < 1 || h < 1 || w > N - x0 || h > N - y0)
+        return fail(PS_E_PARAM, "the region must be non-empty and lie inside the N x N image");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t count = (int64_t)w * h;
+    const int nblk = block_count(count);
+    void *ws = nullptr;
+    if (int rc = get_workspace(stream, (size_t)n * nblk * 8 + (size_t)n * 16 + 1024, &ws)) return rc;
+    Carver c;
+    char *base = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(base + c.take((size_t)n * nblk * 8));
+    double *mean = reinterpret_cast<double *>(base + c.take((size_t)n * 8));
+    double *var = reinterpret_cast<double *>(base + c.take((size_t)n * 8));
+    const bool f64 = dtype == PS_F64;
+    const char *first = static_cast<const char *>(I) + ((size_t)y0 * N + x0) * real_bytes(dtype);
+    HIP_TRY(launch_region_sums(first, nn(N), w, h, N, n, nullptr, 1, nblk, f64, part, stream));
+    HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0 / (double)count, mean, stream));
+    HIP_TRY(launch_region_sums(first, nn(N), w, h, N, n, mean, 2, nblk, f64, part, stream));
+    HIP_TRY(launch_finalize_sums(part, nblk, n, 1.0 / (double)count, var, stream));
     std::vector<double> hm(n), hv(n);
     HIP_TRY(hipMemcpyAsync(hm.data(), mean, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipMemcpyAsync(hv.data(), var, (size_t)n * 8, hipMemcpyDeviceToHost, stream));

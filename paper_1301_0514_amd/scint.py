@@ -41,6 +41,11 @@ SIGNATURES = {
     "fresnel_propagate_vjp": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _vp, _c_int, _c_int,
                                        _vp, _dp, _vp]),
     "ps_modulation_index": (_c_int, [_c_int, _vp, _c_int, _c_int, _dp, _dp, _vp]),
+    "fresnel_aperture": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_dbl, _c_int, _c_int, _vp, _vp]),
+    "ps_aperture_geometry": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _c_dbl, _c_dbl, _dp,
+                                      ctypes.POINTER(_c_int)]),
+    "ps_modulation_index_region": (_c_int, [_c_int, _vp, _c_int, _c_int, _c_int, _c_int, _c_int, _c_int, _dp, _dp,
+                                            _vp]),
     "ps_l2_loss": (_c_int, [_c_int, _vp, _vp, _c_int, _c_int, _vp, _dp, _vp]),
     "ps_last_error": (ctypes.c_char_p, []),
     "ps_last_warning": (ctypes.c_char_p, []),
@@ -214,6 +219,31 @@ def fresnel_propagate(phi: torch.Tensor, delta, lam, z, phase_scale=1.0,
     return out
 
 
+def fresnel_aperture(phi: torch.Tensor, delta, lam, z, phase_scale=1.0, margin_rf=10.0,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """Aperture mode: one-FFT Fresnel pattern of the windowed screen on the
+    observer grid of pixel lam z / (N delta); see scint.h."""
+    N = phi.shape[-1]
+    n = _batch_of(phi, N)
+    if out is None:
+        out = torch.empty_like(phi)
+    rc = load_library().fresnel_aperture(int(N), float(delta), float(lam), float(z), _ptr(phi), float(phase_scale),
+                                         float(margin_rf), n, _dtype_code(phi.dtype), _ptr(out), _stream(phi.device))
+    _check("fresnel_aperture", rc)
+    return out
+
+
+def aperture_geometry(N, delta, lam, z, r_diff, r_s=0.0):
+    """(observer pixel, fiducial margin in observer pixels) of the aperture
+    mode; host arithmetic, see scint.h."""
+    pix = ctypes.c_double(0.0)
+    margin = _c_int(0)
+    rc = load_library().ps_aperture_geometry(int(N), float(delta), float(lam), float(z), float(r_diff), float(r_s),
+                                             ctypes.byref(pix), ctypes.byref(margin))
+    _check("ps_aperture_geometry", rc)
+    return pix.value, margin.value
+
+
 def ps_screen_fresnel(N, delta, r_diff, beta, seed, lam, z, first_realisation=0, n_real=1,
                       dtype=torch.float32, want_phi=False, device=None):
     """Screen generation and propagation fused; returns I (and phi if asked)."""
@@ -283,6 +313,20 @@ def ps_modulation_index(I: torch.Tensor, want_mean=False):
     rc = load_library().ps_modulation_index(int(N), _ptr(I), n, _dtype_code(I.dtype), m, mean,
                                             _stream(I.device))
     _check("ps_modulation_index", rc)
+    ms = [m[i] for i in range(n)]
+    return (ms, [mean[i] for i in range(n)]) if want_mean else ms
+
+
+def ps_modulation_index_region(I: torch.Tensor, x0: int, y0: int, w: int, h: int, want_mean=False):
+    """m (and the mean) over the w x h rectangle starting at pixel (x0, y0) of
+    each pattern, e.g. a fiducial zone; synchronises."""
+    N = I.shape[-1]
+    n = _batch_of(I, N)
+    m = (ctypes.c_double * n)()
+    mean = (ctypes.c_double * n)()
+    rc = load_library().ps_modulation_index_region(int(N), _ptr(I), n, int(x0), int(y0), int(w), int(h),
+                                                   _dtype_code(I.dtype), m, mean, _stream(I.device))
+    _check("ps_modulation_index_region", rc)
     ms = [m[i] for i in range(n)]
     return (ms, [mean[i] for i in range(n)]) if want_mean else ms
 

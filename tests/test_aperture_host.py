@@ -1,0 +1,84 @@
+"""Host-side logic of the aperture mode: argument validation (before any
+device call) and the observer-grid / fiducial-zone geometry (Sect. 3.2.1),
+checked against the configuration the paper prints for Fig. pattern."""
+import ctypes
+import math
+
+import pytest
+
+from tests._golden import paper_values
+
+PC = 3.0856775814913673e16  # metres
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1301_0514_amd import scint
+    try:
+        return scint.load_library()
+    except FileNotFoundError:
+        pytest.skip("libscint.so not built")
+
+
+def _vp(x):
+    return ctypes.c_void_p(x)
+
+
+def test_aperture_validation_codes(lib):
+    ok, other = _vp(1 << 20), _vp(1 << 30)
+    a = lib.fresnel_aperture
+    # N = 256, delta = 1, lambda z = 256: N delta^2 = lambda z (conjugate planes)
+    assert a(256, 1.0, 1.0, 256.0, None, 1.0, 10.0, 1, 0, other, None) == -1
+    assert a(257, 1.0, 1.0, 256.0, ok, 1.0, 10.0, 1, 0, other, None) == -2
+    assert a(256, 1.0, 1.0, 256.0, ok, 1.0, 10.0, 1, 5, other, None) == -4
+    assert a(256, 0.0, 1.0, 256.0, ok, 1.0, 10.0, 1, 0, other, None) == -3
+    assert a(256, 1.0, 1.0, 256.0, ok, float("nan"), 10.0, 1, 0, other, None) == -3
+    assert a(256, 1.0, 1.0, 256.0, ok, 1.0, -1.0, 1, 0, other, None) == -3
+    # N delta^2 > lambda z: the chirp is undersampled at the border
+    assert a(256, 1.0, 1.0, 200.0, ok, 1.0, 10.0, 1, 0, other, None) == -3
+    assert b"undersampled" in lib.ps_last_error()
+    # exactly at the conjugate relation is accepted (fails later on the alias)
+    assert a(256, 1.0, 1.0, 256.0, ok, 1.0, 10.0, 1, 0, _vp((1 << 20) + 64), None) == -7
+    # window margins wider than the screen: 2 * 30 * rho > N
+    assert a(256, 1.0, 1.0, 256.0, ok, 1.0, 30.0, 1, 0, other, None) == -3
+    assert b"margin" in lib.ps_last_error()
+    r = lib.ps_modulation_index_region
+    m = (ctypes.c_double * 1)()
+    assert r(256, ok, 1, 0, 0, 256, 256, 0, None, None, None) == -1
+    for (x0, y0, w, h) in ((-1, 0, 10, 10), (0, 0, 0, 10), (250, 0, 7, 1), (0, 250, 1, 7), (0, 0, 257, 1)):
+        assert r(256, ok, 1, x0, y0, w, h, 0, m, None, None) == -3
+
+
+def test_aperture_geometry_matches_the_papers_pattern(lib):
+    pv = paper_values()
+    from paper_1301_0514_amd import scint
+    lam = pv["pattern_lambda_um"] * 1e-6
+    z = pv["pattern_z_pc"] * PC
+    rf = math.sqrt(lam * z / (2 * math.pi))
+    assert rf / 1e3 == pytest.approx(pv["pattern_rf_km"], rel=0.01)
+    # conjugate planes (Sect. 3.4): N delta^2 = 2 pi R_F^2 -> observer pixel = delta
+    N = 20000
+    delta = math.sqrt(2 * math.pi * rf ** 2 / N)
+    pix, margin = scint.aperture_geometry(N, delta, lam, z, pv["pattern_rdiff_km"] * 1e3)
+    assert pix == pytest.approx(delta, rel=1e-12)
+    r_ref = 2 * math.pi * rf ** 2 / (pv["pattern_rdiff_km"] * 1e3)
+    assert r_ref / 1e3 == pytest.approx(pv["pattern_rref_km"], rel=0.1)
+    assert margin == math.ceil(0.5 * r_ref / pix)
+    # the extended-source zone adds R_s
+    pix2, margin2 = scint.aperture_geometry(N, delta, lam, z, pv["pattern_rdiff_km"] * 1e3,
+                                            pv["extended_rs_km"] * 1e3)
+    assert pix2 == pix and margin2 == math.ceil((0.5 * r_ref + pv["extended_rs_km"] * 1e3) / pix)
+    # a coarser screen pixel: observer pixel lambda z / (N delta)
+    pix3, _ = scint.aperture_geometry(N, 2 * delta, lam, z, 1e5)
+    assert pix3 == pytest.approx(delta / 2, rel=1e-12)
+
+
+def test_aperture_geometry_validation(lib):
+    from paper_1301_0514_amd import scint
+    with pytest.raises(scint.ScintError):
+        scint.aperture_geometry(256, 1.0, 1.0, 256.0, 0.0)
+    with pytest.raises(scint.ScintError):
+        scint.aperture_geometry(256, 1.0, 1.0, 256.0, 1.0, -1.0)
+    # an empty fiducial zone is reported as a warning, the margin capped at N
+    pix, margin = scint.aperture_geometry(256, 1.0, 1.0, 256.0, 0.5)
+    assert margin == 256 and b"empty" in lib.ps_last_warning()
