@@ -72,6 +72,8 @@ def _load():
                 "oracle_fresnel_aperture": (None, [c_int, c_dbl, c_dbl, c_dbl, dp, dp]),
                 "oracle_fresnel_aperture_direct": (None, [c_int, c_dbl, c_dbl, c_dbl, dp, dp]),
                 "oracle_modulation_index_region": (c_dbl, [c_int, dp, c_int, c_int, c_int, c_int, dp]),
+                "oracle_light_curves": (None, [c_int, dp, c_int, dp, c_int, c_int, dp, dp]),
+                "oracle_m_theory": (c_dbl, [c_dbl, c_dbl, c_dbl]),
                 "oracle_propagate_vjp": (None, [c_int, c_dbl, c_dbl, dp, dp, dp]),
                 "oracle_propagate_adjoint_field": (None, [c_int, c_dbl, dp, dp]),
                 "oracle_propagate_field": (None, [c_int, c_dbl, dp, dp]),
@@ -256,6 +258,26 @@ def modulation_index_region(I, x0: int, y0: int, w: int, h: int):
     mean = ctypes.c_double(0.0)
     m = _load().oracle_modulation_index_region(I.shape[0], _dp(I), x0, y0, w, h, ctypes.byref(mean))
     return m, mean.value
+
+
+def light_curves(I, lines, n_samples: int, mode: int = 0):
+    """Light curves (Sect. 3.3): samples of the periodic pattern I along
+    straight lines, lines[l] = (x0, y0, dx, dy) in pixels (pixel (ix, iy) at the
+    integer point), mode 0 nearest pixel, 1 bilinear.  Returns (curves
+    [n_lines, n_samples], m per curve)."""
+    I = _f64(I)
+    L = _f64(np.atleast_2d(lines))
+    n_lines = L.shape[0]
+    curves = np.zeros((n_lines, n_samples), dtype=np.float64)
+    m = np.zeros(n_lines, dtype=np.float64)
+    _load().oracle_light_curves(I.shape[0], _dp(I), n_lines, _dp(L), n_samples, mode, _dp(curves), _dp(m))
+    return curves, m
+
+
+def m_theory(r_diff: float, r_f: float, r_s: float) -> float:
+    """Expected m of an extended source, strong quenched regime, Kolmogorov
+    (Sect. 4.1, Eq. xparam): (R_diff/R_F)^(1/3) (R_ref/(2 pi R_s))^(7/6)."""
+    return _load().oracle_m_theory(r_diff, r_f, r_s)
 
 
 def propagate_field(field, rho: float) -> np.ndarray:

@@ -28,6 +28,10 @@
  *                              it, the window's closed-form values, Parseval,
  *                              and the paper's < 1 % flatness for a uniform
  *                              screen
+ *   light curves, m theory   : axis-aligned lines equal pattern rows and
+ *                              columns, bilinear sampling is exact on linear
+ *                              fields and equals the pixels at integer points;
+ *                              the paper's numeric form of Eq. xparam
  *   Propagation at a general rho (N != 2 pi rho^2) beyond the closed forms
  *   above is "parity unpinned" as physics; its algebra is pinned by the DFT.
  */
@@ -629,6 +633,68 @@ double oracle_modulation_index_region(int N, const double *inten, int x0, int y0
         }
     if (mean_out) *mean_out = mean;
     return sqrt(v / cnt) / mean;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Light curves (Sect. 3.3): the pattern sampled along straight lines at a  */
+/* constant relative speed.  Pixel (ix, iy) sits at the integer point       */
+/* (ix, iy); sample k of a line lies at (x0 + k dx, y0 + k dy) in pixels,   */
+/* wrapped onto the periodic pattern.  mode 0 takes the pixel nearest to    */
+/* the point, mode 1 interpolates bilinearly between the four around it.    */
+/* m of each curve as in Sect. 4 (population sigma over the samples).       */
+/* ------------------------------------------------------------------------ */
+
+static long wrap_index(double v, int N)
+{
+    long i = (long)floor(v);
+    long r = i % N;
+    return r < 0 ? r + N : r;
+}
+
+void oracle_light_curves(int N, const double *inten, int n_lines, const double *lines, int n_samples,
+                         int mode, double *curves, double *m_out)
+{
+    for (int l = 0; l < n_lines; ++l) {
+        const double x0 = lines[4 * l], y0 = lines[4 * l + 1], dx = lines[4 * l + 2], dy = lines[4 * l + 3];
+        double *c = curves + (size_t)l * n_samples;
+        for (int k = 0; k < n_samples; ++k) {
+            double x = x0 + k * dx, y = y0 + k * dy;
+            if (mode == 0) {
+                long ix = wrap_index(x + 0.5, N), iy = wrap_index(y + 0.5, N);
+                c[k] = inten[(size_t)iy * N + ix];
+            } else {
+                double fx = x - floor(x), fy = y - floor(y);
+                long ix = wrap_index(x, N), iy = wrap_index(y, N);
+                long jx = (ix + 1) % N, jy = (iy + 1) % N;
+                c[k] = (1 - fx) * (1 - fy) * inten[(size_t)iy * N + ix] + fx * (1 - fy) * inten[(size_t)iy * N + jx] +
+                       (1 - fx) * fy * inten[(size_t)jy * N + ix] + fx * fy * inten[(size_t)jy * N + jx];
+            }
+        }
+        if (m_out) {
+            double s = 0.0, cc = 0.0;
+            for (int k = 0; k < n_samples; ++k) {
+                double yv = c[k] - cc, t = s + yv;
+                cc = (t - s) - yv; s = t;
+            }
+            double mean = s / n_samples, v = 0.0;
+            cc = 0.0;
+            for (int k = 0; k < n_samples; ++k) {
+                double d = c[k] - mean, yv = d * d - cc, t = v + yv;
+                cc = (t - v) - yv; v = t;
+            }
+            m_out[l] = sqrt(v / n_samples) / mean;
+        }
+    }
+}
+
+/* Expected modulation index of an extended source in the strong, quenched */
+/* regime for Kolmogorov turbulence (Sect. 4.1, Eq. xparam, after Narayan  */
+/* 1992): m = (R_diff/R_F)^(1/3) (R_ref / (2 pi R_s))^(7/6) with           */
+/* R_ref = 2 pi R_F^2 / R_diff; any one length unit.                        */
+double oracle_m_theory(double r_diff, double r_f, double r_s)
+{
+    double r_ref = 2.0 * ORACLE_PI * r_f * r_f / r_diff;
+    return pow(r_diff / r_f, 1.0 / 3.0) * pow(r_ref / (2.0 * ORACLE_PI * r_s), 7.0 / 6.0);
 }
 
 /* ------------------------------------------------------------------------ */
