@@ -31,20 +31,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# device sources of the row-pass kernels (the FFT passes that dominate the step)
+ROW_KERNEL_SOURCES = ("device_common.hpp", "fft_plan.hpp", "row_program.h", "row_kernel.hpp", "row_launch.h",
+                      "row_inst.hip", "twiddles.cpp")
+
+
 def source_hash() -> str:
-    """Hash of the kernel sources; ties a stored counter profile to a build."""
+    """Hash of the row-pass kernel sources; ties a stored counter profile to
+    the kernel it was taken on."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1301_0514_amd", "csrc", "*"))):
-        if p.endswith((".hip", ".hpp", ".h", ".cpp")):
-            with open(p, "rb") as fh:
-                h.update(os.path.basename(p).encode())
-                h.update(fh.read())
+    for name in ROW_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1301_0514_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str):
+def stored_traffic(kernel: str, plan_variant: int | None = None):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
-    summary (profiles/traffic_*.txt), if it was taken on the current sources."""
+    summary (profiles/traffic_*.txt), if it was taken on the current kernel
+    sources and FFT plan variant."""
     want = source_hash()
     for p in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt")):
         vals = {}
@@ -53,6 +59,8 @@ def stored_traffic(kernel: str):
                 if "=" in line and not line.lstrip().startswith("#"):
                     k, v = (t.strip() for t in line.split("=", 1))
                     vals[k] = v
+        if plan_variant is not None and vals.get("plan_variant") not in (None, str(plan_variant)):
+            continue
         if vals.get("kernel") == kernel and vals.get("source_sha256") == want:
             try:
                 return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
@@ -169,7 +177,12 @@ def main(argv=None) -> int:
     flops_per_launch = d["flops"] / d["launches"]
     gbps = bytes_per_launch / (avg_ms / 1e3) / 1e9
     tflops = flops_per_launch / (avg_ms / 1e3) / 1e12
-    traffic = stored_traffic(dname)
+    # plan variant the dominant kernel ran with (row passes are named row_<program>_<dtype>_N<size>)
+    try:
+        dom_variant = scint.plan_variant(int(dname.rsplit("_N", 1)[1]), torch.float32)[0]
+    except (IndexError, ValueError, scint.ScintError):
+        dom_variant = None
+    traffic = stored_traffic(dname, dom_variant)
     kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                    "avg_launch_ms": v["ms"] / v["launches"],
                    "algorithmic_GBps": (v["bytes"] / v["launches"]) / (v["ms"] / v["launches"] / 1e3) / 1e9,
@@ -349,6 +362,24 @@ def main(argv=None) -> int:
         sec["aperture_8192_fresnel"] = {"ms_per_call": ta, "pt_per_s": Na ** 2 / (ta / 1e3)}
         log("aperture mode 8192^2: %.3f ms" % ta)
         del Ia
+
+        # m against Eq. xparam (Sect. 4.1, Fig. mx), periodic mode on the
+        # paper's geometry, 16 realisations per configuration
+        from statistics import mean as _mean
+        from paper_1301_0514_amd import sweep
+        t0 = time.perf_counter()
+        pts = sweep.m_versus_theory(8192, 25.0, 2.162e-6, 160 * sweep.PC, 1000 * sweep.PC, [200, 300, 400, 500],
+                                    [0.25, 0.5], n_real=16, mode="periodic")
+        t_sweep = time.perf_counter() - t0
+        rows = []
+        for rd in (200, 300, 400, 500):
+            for rs in (0.25, 0.5):
+                g = [p for p in pts if p.r_diff_km == rd and p.r_s_rsun == rs]
+                rows.append({"r_diff_km": rd, "r_s_rsun": rs, "m_theory": g[0].m_theory,
+                             "m_mean": _mean(p.m for p in g), "ratio_mean": _mean(p.m / p.m_theory for p in g),
+                             "n_ref": g[0].n_ref})
+        sec["m_versus_theory_8192"] = {"seconds": t_sweep, "patterns": len(pts), "rows": rows}
+        log("m sweep: %d patterns in %.2f s" % (len(pts), t_sweep))
 
         # forward + adjoint, 16 x 2048^2
         g = presets.GRAD_2048

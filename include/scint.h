@@ -204,8 +204,10 @@ int fresnel_aperture(int N, double delta, double lambda, double z, const void *p
 /*
  * ps_aperture_geometry -- the observer grid of fresnel_aperture and its
  * fiducial zone (Sect. 3.2.1): observer_pixel = lambda z / (N delta) (length
- * unit of delta), and fiducial_margin = ceil((R_ref / 2 + r_s) /
- * observer_pixel) pixels to exclude at each border, R_ref = lambda z / r_diff
+ * unit of delta), and fiducial_margin = the number of observer pixels to
+ * exclude at each border: the dark rim outside the screen's shadow,
+ * N (1 - delta / observer_pixel) / 2 (zero at N delta^2 = lambda z), plus
+ * (R_ref / 2 + r_s) / observer_pixel, rounded up; R_ref = lambda z / r_diff
  * (= 2 pi R_F^2 / R_diff, the refractive scale) and r_s the projected source
  * radius (0 for a point source; the extended-source zone adds R_s).  Host
  * arithmetic only.  A warning is set when the zone is empty
@@ -234,6 +236,37 @@ int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out,
  */
 int ps_modulation_index_region(int N, const void *I, int n, int x0, int y0, int w, int h,
                                int dtype, double *m_out, double *mean_out, void *hip_stream);
+
+/*
+ * ps_light_curves -- light curves as a telescope sweeping the pattern sees
+ * them (Sect. 3.3): each pattern is sampled along straight lines at a
+ * constant speed.  Pixel (ix, iy) sits at the point (ix, iy) in pixel units;
+ * sample k of line l lies at (x0 + k dx, y0 + k dy) with
+ * lines[4 l .. 4 l + 3] = (x0, y0, dx, dy), wrapped onto the periodic
+ * pattern.  mode 0 takes the nearest pixel (ties round up), mode 1
+ * interpolates bilinearly between the four surrounding pixels (FP64
+ * weights).  (dx, dy) is the relative transverse velocity times the sampling
+ * interval, in pixels.
+ *   I           device [n][N][N] real
+ *   lines       host array of 4 n_lines finite doubles (n_lines >= 1)
+ *   curves_out  device [n][n_lines][n_samples] real; must not overlap I
+ *   m_out       optional host array of n n_lines doubles: sigma/mean of each
+ *               curve (population sigma, FP64, Sect. 4); the call then
+ *               synchronises with the stream
+ */
+int ps_light_curves(int N, const void *I, int n, const double *lines, int n_lines,
+                    int n_samples, int mode, int dtype, void *curves_out, double *m_out,
+                    void *hip_stream);
+
+/*
+ * ps_m_theory -- expected modulation index of an extended source in the
+ * strong, quenched regime for Kolmogorov turbulence (Sect. 4.1, Eq. xparam,
+ * after Narayan 1992): m = (R_diff/R_F)^(1/3) (R_ref / (2 pi R_s))^(7/6),
+ * R_ref = 2 pi R_F^2 / R_diff, with R_s the projected source radius (all in
+ * one length unit, > 0).  Host arithmetic only; a warning is set outside the
+ * regime R_s/R_F > R_F/R_diff > 1 where the relation holds.
+ */
+int ps_m_theory(double r_diff, double r_f, double r_s, double *m_out);
 
 /*
  * ps_l2_loss -- L = sum_m (I - I_target)^2 per pattern and its gradient

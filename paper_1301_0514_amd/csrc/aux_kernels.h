@@ -37,6 +37,18 @@ hipError_t launch_region_sums(const void *x, int64_t batch_stride, int64_t w, in
 // phase is formed and reduced in FP64 turns, the sine/cosine taken in FP64.
 hipError_t launch_aperture_table(void *tab, int N, double a, double Lm, bool f64, hipStream_t stream);
 
+// Light curves: lines of 4 doubles (x0, y0, dx, dy) in pixels, passed by
+// value kLinesPerLaunch at a time; out[b][l][k] = the pattern b sampled at
+// (x0 + k dx, y0 + k dy) (mode 0 nearest pixel, 1 bilinear, periodic);
+// stats[2 (b n_lines + l) + {0, 1}] = mean and population variance (FP64) if
+// stats != NULL.
+constexpr int kLinesPerLaunch = 64;
+struct LineSet {
+    double p[kLinesPerLaunch][4];
+};
+hipError_t launch_light_curves(const void *I, int N, int nbatch, const double *lines, int n_lines, int n_samples,
+                               int mode, bool f64, void *out, double *stats, hipStream_t stream);
+
 // out[b] = scale * sum_blk partials[b * nblk + blk], fixed-order tree.
 hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,
                                 hipStream_t stream);

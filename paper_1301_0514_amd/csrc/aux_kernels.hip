@@ -280,6 +280,86 @@ hipError_t launch_block_sums(const void *x, int64_t n_per_batch, int nbatch, con
                               partials, stream);
 }
 
+// ---------------------------------------------------------------- light curves
+// One workgroup per (pattern, line): sample k of line l lies at
+// (x0 + k dx, y0 + k dy) pixels (pixel (ix, iy) at the integer point), wrapped
+// onto the periodic pattern; mode 0 takes the nearest pixel, mode 1
+// interpolates bilinearly (weights and sum in FP64).  The curve is written
+// and its mean and population variance formed in FP64 in a fixed order.
+__device__ __forceinline__ int64_t wrap_floor(double v, int N) {
+    const int64_t i = (int64_t)floor(v);
+    const int64_t r = i % N;
+    return r < 0 ? r + N : r;
+}
+
+// x0 + k dx with the product and the sum rounded separately (no fused
+// multiply-add), the same position a plain evaluation of the formula gives
+__device__ __forceinline__ double sample_coord(double x0, int k, double dx) {
+#pragma clang fp contract(off)
+    return x0 + (double)k * dx;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void light_curve_kernel(const Real *__restrict__ I, int N, LineSet ls, int n_samples,
+                                                          int mode, Real *__restrict__ out, int n_lines_total,
+                                                          int line0, double *stats) {
+    __shared__ double red[256];
+    const int l = blockIdx.x, b = blockIdx.y;
+    const Real *img = I + (int64_t)b * N * N;
+    Real *c = out + ((int64_t)b * n_lines_total + line0 + l) * n_samples;
+    const double x0 = ls.p[l][0], y0 = ls.p[l][1], dx = ls.p[l][2], dy = ls.p[l][3];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n_samples; k += 256) {
+        const double x = sample_coord(x0, k, dx), y = sample_coord(y0, k, dy);
+        Real v;
+        if (mode == 0) {
+            v = img[wrap_floor(y + 0.5, N) * N + wrap_floor(x + 0.5, N)];
+        } else {
+            const double fx = x - floor(x), fy = y - floor(y);
+            const int64_t ix = wrap_floor(x, N), iy = wrap_floor(y, N);
+            const int64_t jx = ix + 1 == N ? 0 : ix + 1, jy = iy + 1 == N ? 0 : iy + 1;
+            v = (Real)((1.0 - fx) * (1.0 - fy) * (double)img[iy * N + ix] + fx * (1.0 - fy) * (double)img[iy * N + jx] +
+                       (1.0 - fx) * fy * (double)img[jy * N + ix] + fx * fy * (double)img[jy * N + jx]);
+        }
+        c[k] = v;
+        acc += (double)v;
+    }
+    const double mean = block_tree_sum(acc, red) / (double)n_samples;
+    __syncthreads();
+    double acc2 = 0.0;
+    for (int k = threadIdx.x; k < n_samples; k += 256) {  // each thread re-reads its own samples
+        const double d = (double)c[k] - mean;
+        acc2 += d * d;
+    }
+    const double var = block_tree_sum(acc2, red) / (double)n_samples;
+    if (threadIdx.x == 0 && stats) {
+        stats[2 * ((int64_t)b * n_lines_total + line0 + l)] = mean;
+        stats[2 * ((int64_t)b * n_lines_total + line0 + l) + 1] = var;
+    }
+}
+
+hipError_t launch_light_curves(const void *I, int N, int nbatch, const double *lines, int n_lines, int n_samples,
+                               int mode, bool f64, void *out, double *stats, hipStream_t stream) {
+    for (int l0 = 0; l0 < n_lines; l0 += kLinesPerLaunch) {
+        const int nl = n_lines - l0 < kLinesPerLaunch ? n_lines - l0 : kLinesPerLaunch;
+        LineSet ls{};
+        for (int l = 0; l < nl; ++l)
+            for (int q = 0; q < 4; ++q) ls.p[l][q] = lines[4 * (l0 + l) + q];
+        dim3 grid(nl, nbatch);
+        if (f64)
+            hipLaunchKernelGGL((light_curve_kernel<double>), grid, dim3(256), 0, stream,
+                               static_cast<const double *>(I), N, ls, n_samples, mode, static_cast<double *>(out),
+                               n_lines, l0, stats);
+        else
+            hipLaunchKernelGGL((light_curve_kernel<float>), grid, dim3(256), 0, stream,
+                               static_cast<const float *>(I), N, ls, n_samples, mode, static_cast<float *>(out),
+                               n_lines, l0, stats);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 __global__ __launch_bounds__(256) void finalize_kernel(const double *partials, int nblk, double scale, double *out) {
     __shared__ double red[256];
     const int b = blockIdx.x;

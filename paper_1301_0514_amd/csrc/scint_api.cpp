@@ -904,7 +904,10 @@ int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_
     if (!(std::isfinite(r_s) && r_s >= 0.0)) return fail(PS_E_PARAM, "r_s must be finite and >= 0");
     const double pix0 = lambda * z / ((double)N * delta);
     const double r_ref = lambda * z / r_diff;  // 2 pi R_F^2 / R_diff
-    const double m = std::ceil((0.5 * r_ref + r_s) / pix0);
+    // the illuminated pattern is the screen's shadow, N delta wide, centred on
+    // the observer grid (N pix0 wide, pix0 >= delta when fresnel_aperture runs)
+    const double rim = std::max(0.0, 0.5 * (double)N * (1.0 - delta / pix0));
+    const double m = std::ceil(rim + (0.5 * r_ref + r_s) / pix0 - 1e-9);
     *observer_pixel = pix0;
     *fiducial_margin = m > (double)N ? N : (int)m;
     if (2.0 * m >= (double)N) g_last_warning = "the fiducial zone is empty at this geometry";
@@ -1260,6 +1263,51 @@ int ps_modulation_index_region(int N, const void *I, int n, int x0, int y0, int 
         m_out[b] = std::sqrt(hv[b]) / hm[b];
         if (mean_out) mean_out[b] = hm[b];
     }
+    return PS_OK;
+}
+
+int ps_light_curves(int N, const void *I, int n, const double *lines, int n_lines, int n_samples, int mode,
+                    int dtype, void *curves_out, double *m_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!I || !lines || !curves_out) return fail(PS_E_NULL, "I, lines and curves_out must be non-NULL");
+    if (int rc = check_aligned({I, curves_out})) return rc;
+    if (n_lines < 1 || n_samples < 1) return fail(PS_E_SIZE, "n_lines and n_samples must be >= 1");
+    if (mode != 0 && mode != 1) return fail(PS_E_PARAM, "mode must be 0 (nearest pixel) or 1 (bilinear)");
+    for (int i = 0; i < 4 * n_lines; ++i)
+        if (!std::isfinite(lines[i])) return fail(PS_E_PARAM, "line coordinates must be finite");
+    const size_t ib = (size_t)nn(N) * real_bytes(dtype) * n;
+    const size_t cb = (size_t)n * n_lines * n_samples * real_bytes(dtype);
+    if (overlaps(I, ib, curves_out, cb)) return fail(PS_E_ALIAS, "curves_out overlaps I");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    double *stats = nullptr;
+    if (m_out) {
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, (size_t)n * n_lines * 16 + 256, &ws)) return rc;
+        stats = static_cast<double *>(ws);
+    }
+    HIP_TRY(launch_light_curves(I, N, n, lines, n_lines, n_samples, mode, dtype == PS_F64, curves_out, stats,
+                                stream));
+    if (m_out) {
+        std::vector<double> h((size_t)2 * n * n_lines);
+        HIP_TRY(hipMemcpyAsync(h.data(), stats, h.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (size_t i = 0; i < (size_t)n * n_lines; ++i) m_out[i] = std::sqrt(h[2 * i + 1]) / h[2 * i];
+    }
+    return PS_OK;
+}
+
+int ps_m_theory(double r_diff, double r_f, double r_s, double *m_out) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (!m_out) return fail(PS_E_NULL, "m_out is NULL");
+    if (!finite_pos(r_diff) || !finite_pos(r_f) || !finite_pos(r_s))
+        return fail(PS_E_PARAM, "r_diff, r_f and r_s must be finite and > 0");
+    const double r_ref = 2.0 * kPiD * r_f * r_f / r_diff;
+    *m_out = std::pow(r_diff / r_f, 1.0 / 3.0) * std::pow(r_ref / (2.0 * kPiD * r_s), 7.0 / 6.0);
+    if (!(r_s / r_f > r_f / r_diff && r_f / r_diff > 1.0))
+        g_last_warning = "outside the strong, quenched regime R_s/R_F > R_F/R_diff > 1";
     return PS_OK;
 }
 

@@ -46,6 +46,8 @@ SIGNATURES = {
                                       ctypes.POINTER(_c_int)]),
     "ps_modulation_index_region": (_c_int, [_c_int, _vp, _c_int, _c_int, _c_int, _c_int, _c_int, _c_int, _dp, _dp,
                                             _vp]),
+    "ps_light_curves": (_c_int, [_c_int, _vp, _c_int, _dp, _c_int, _c_int, _c_int, _c_int, _vp, _dp, _vp]),
+    "ps_m_theory": (_c_int, [_c_dbl, _c_dbl, _c_dbl, _dp]),
     "ps_l2_loss": (_c_int, [_c_int, _vp, _vp, _c_int, _c_int, _vp, _dp, _vp]),
     "ps_last_error": (ctypes.c_char_p, []),
     "ps_last_warning": (ctypes.c_char_p, []),
@@ -329,6 +331,34 @@ def ps_modulation_index_region(I: torch.Tensor, x0: int, y0: int, w: int, h: int
     _check("ps_modulation_index_region", rc)
     ms = [m[i] for i in range(n)]
     return (ms, [mean[i] for i in range(n)]) if want_mean else ms
+
+
+def light_curves(I: torch.Tensor, lines, n_samples: int, mode: int = 0, want_m: bool = True):
+    """Samples of each pattern along straight lines (x0, y0, dx, dy) in pixels
+    (Sect. 3.3): returns curves [n, n_lines, n_samples] and, if asked, m of
+    each curve as a nested list [n][n_lines] (synchronises); see scint.h."""
+    N = I.shape[-1]
+    n = _batch_of(I, N)
+    flat = [float(v) for line in lines for v in line]
+    n_lines = len(flat) // 4
+    if n_lines * 4 != len(flat) or n_lines < 1:
+        raise ValueError("lines must be a non-empty list of (x0, y0, dx, dy)")
+    arr = (ctypes.c_double * len(flat))(*flat)
+    curves = torch.empty((n, n_lines, int(n_samples)), dtype=I.dtype, device=I.device)
+    m = (ctypes.c_double * (n * n_lines))() if want_m else None
+    rc = load_library().ps_light_curves(int(N), _ptr(I), n, arr, n_lines, int(n_samples), int(mode),
+                                        _dtype_code(I.dtype), _ptr(curves), m, _stream(I.device))
+    _check("ps_light_curves", rc)
+    if not want_m:
+        return curves
+    return curves, [[m[b * n_lines + l] for l in range(n_lines)] for b in range(n)]
+
+
+def m_theory(r_diff, r_f, r_s) -> float:
+    """Expected m of an extended source (Sect. 4.1, Eq. xparam); host only."""
+    m = ctypes.c_double(0.0)
+    _check("ps_m_theory", load_library().ps_m_theory(float(r_diff), float(r_f), float(r_s), ctypes.byref(m)))
+    return m.value
 
 
 def ps_l2_loss(I: torch.Tensor, I_target: torch.Tensor, want_grad=True):

@@ -71,6 +71,13 @@ def test_aperture_geometry_matches_the_papers_pattern(lib):
     # a coarser screen pixel: observer pixel lambda z / (N delta)
     pix3, _ = scint.aperture_geometry(N, 2 * delta, lam, z, 1e5)
     assert pix3 == pytest.approx(delta / 2, rel=1e-12)
+    # a finer screen pixel (N delta^2 < lambda z): the screen's shadow covers
+    # N delta / pix of the N observer pixels, and the zone starts R_ref/2
+    # inside the shadow's border
+    d4 = 0.6 * delta
+    pix4, margin4 = scint.aperture_geometry(N, d4, lam, z, 1e5)
+    shadow = N * d4 / pix4
+    assert margin4 == math.ceil((N - shadow) / 2 + 0.5 * (lam * z / 1e5) / pix4)
 
 
 def test_aperture_geometry_validation(lib):
@@ -82,3 +89,28 @@ def test_aperture_geometry_validation(lib):
     # an empty fiducial zone is reported as a warning, the margin capped at N
     pix, margin = scint.aperture_geometry(256, 1.0, 1.0, 256.0, 0.5)
     assert margin == 256 and b"empty" in lib.ps_last_warning()
+
+
+def test_light_curve_validation_codes(lib):
+    ok, other = _vp(1 << 20), _vp(1 << 30)
+    f = lib.ps_light_curves
+    lines = (ctypes.c_double * 8)(0.0, 1.0, 1.0, 0.0, 2.0, 3.0, 0.5, 0.5)
+    bad = (ctypes.c_double * 4)(0.0, float("nan"), 1.0, 0.0)
+    assert f(256, ok, 1, None, 2, 100, 0, 0, other, None, None) == -1
+    assert f(256, ok, 1, lines, 0, 100, 0, 0, other, None, None) == -2
+    assert f(256, ok, 1, lines, 2, 0, 0, 0, other, None, None) == -2
+    assert f(256, ok, 1, lines, 2, 100, 2, 0, other, None, None) == -3
+    assert f(256, ok, 1, bad, 1, 100, 0, 0, other, None, None) == -3
+    assert f(256, ok, 1, lines, 2, 100, 0, 0, _vp((1 << 20) + 1024), None, None) == -7
+
+
+def test_m_theory_host(lib, oracle):
+    from paper_1301_0514_amd import scint
+    for r_diff, r_f, r_s in [(100.0, 1300.0, 53000.0), (300.0, 1000.0, 41000.0), (50.0, 1300.0, 2.0e5)]:
+        assert scint.m_theory(r_diff, r_f, r_s) == pytest.approx(oracle.m_theory(r_diff, r_f, r_s), rel=1e-14)
+        assert lib.ps_last_warning() == b""
+    # outside the strong, quenched regime the relation is flagged
+    scint.m_theory(2000.0, 1300.0, 53000.0)
+    assert b"quenched" in lib.ps_last_warning()
+    with pytest.raises(scint.ScintError):
+        scint.m_theory(0.0, 1.0, 1.0)
