@@ -73,6 +73,7 @@ def _load():
                 "oracle_fresnel_aperture_direct": (None, [c_int, c_dbl, c_dbl, c_dbl, dp, dp]),
                 "oracle_modulation_index_region": (c_dbl, [c_int, dp, c_int, c_int, c_int, c_int, dp]),
                 "oracle_light_curves": (None, [c_int, dp, c_int, dp, c_int, c_int, dp, dp]),
+                "oracle_propagate_line": (None, [c_int, c_dbl, c_dbl, dp, dp]),
                 "oracle_m_theory": (c_dbl, [c_dbl, c_dbl, c_dbl]),
                 "oracle_propagate_vjp": (None, [c_int, c_dbl, c_dbl, dp, dp, dp]),
                 "oracle_propagate_adjoint_field": (None, [c_int, c_dbl, dp, dp]),
@@ -278,6 +279,15 @@ def m_theory(r_diff: float, r_f: float, r_s: float) -> float:
     """Expected m of an extended source, strong quenched regime, Kolmogorov
     (Sect. 4.1, Eq. xparam): (R_diff/R_F)^(1/3) (R_ref/(2 pi R_s))^(7/6)."""
     return _load().oracle_m_theory(r_diff, r_f, r_s)
+
+
+def propagate_line(phi_1d, rho: float, s: float = 1.0) -> np.ndarray:
+    """Field a = N^-1 IDFT[H1 DFT exp(i s phi)] along one line of N pixels;
+    for phi(x, y) = f(x) + g(y) the 2-D intensity is |a_g(y)|^2 |a_f(x)|^2."""
+    phi = _f64(phi_1d)
+    out = np.zeros(phi.shape[0], dtype=np.complex128)
+    _load().oracle_propagate_line(phi.shape[0], rho, s, _dp(phi), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
 
 
 def propagate_field(field, rho: float) -> np.ndarray:

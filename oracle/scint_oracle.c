@@ -357,6 +357,26 @@ void oracle_propagate(int N, double rho, double s, const double *phi, double *I_
     free(a);
 }
 
+/* One-dimensional counterpart along a line of N pixels: a = N^-1 IDFT[H1  */
+/* DFT exp(i s phi)].  For a separable screen phi(x, y) = f(x) + g(y) the     */
+/* 2-D field of oracle_propagate is the outer product a_g(y) a_f(x), since   */
+/* both the DFT and H = H1(kx) H1(ky) factorise.                             */
+void oracle_propagate_line(int N, double rho, double s, const double *phi, double *a_ri)
+{
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    for (int x = 0; x < N; ++x) a[x] = expi_turns(s * phi[x] / (2.0 * ORACLE_PI));
+    cplx *fwd = make_roots(N, -1), *inv = make_roots(N, +1);
+    dft_rec(N, a, 1, b, fwd, N);
+    for (int k = 0; k < N; ++k) b[k] *= chirp1(k, N, rho) / (double)N;
+    dft_rec(N, b, 1, a, inv, N);
+    free(fwd);
+    free(inv);
+    memcpy(a_ri, a, sizeof(cplx) * (size_t)N);
+    free(b);
+    free(a);
+}
+
 /* Same, physical arguments (any one length unit for delta, lambda, z). */
 void oracle_fresnel(int N, double delta, double lambda, double z, double s,
                     const double *phi, double *I_out)

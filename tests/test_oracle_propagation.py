@@ -139,3 +139,25 @@ def test_physical_arguments(oracle):
     assert oracle.fresnel_radius_px(delta, lam, z) == pytest.approx(rho, rel=1e-15)
     phi = oracle.screen(N, 3.0, 11 / 3, seed=2, r=0)
     assert np.array_equal(oracle.fresnel(phi, delta, lam, z), oracle.propagate(phi, rho))
+
+
+@pytest.mark.parametrize("N,rho,s", [(16, None, 1.0), (64, None, 0.7), (40, 7.0, 0.8), (64, 3.0, 1.3),
+                                     (100, 20.0, 1.0)])
+def test_separable_screen_factorises(oracle, N, rho, s):
+    conjugate = rho is None
+    if conjugate:
+        rho = np.sqrt(N / (2 * np.pi))
+    # phi(x, y) = f(x) + g(y): the 2-D propagation is the outer product of two
+    # 1-D propagations (the DFT and H = H1(kx) H1(ky) both factorise)
+    rng = np.random.default_rng(N)
+    f, g = rng.uniform(-3, 3, N), rng.uniform(-3, 3, N)
+    I2 = oracle.propagate(g[:, None] + f[None, :], rho, s)
+    af, ag = oracle.propagate_line(f, rho, s), oracle.propagate_line(g, rho, s)
+    I1 = np.outer(np.abs(ag) ** 2, np.abs(af) ** 2)
+    assert np.abs(I2 - I1).max() < 1e-12 * I2.max()
+    # and at the conjugate planes the 1-D line equals the direct 1-D Fresnel sum
+    if conjugate:
+        m = np.arange(N)
+        k = np.exp(1j * np.pi * ((m[:, None] - m[None, :]) ** 2) / N)  # e^{i (x0-x1)^2 / 2 rho^2}
+        a_direct = k @ np.exp(1j * s * f) / np.sqrt(N) * np.exp(-1j * np.pi / 4)
+        assert np.abs(np.abs(a_direct) ** 2 - np.abs(af) ** 2).max() < 1e-12
