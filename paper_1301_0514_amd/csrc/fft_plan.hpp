@@ -72,6 +72,9 @@ SCINT_PLAN(4000, 20, 20, 20, 10)
 SCINT_PLAN(5000, 10, 10, 10, 10, 5)
 SCINT_PLAN(8000, 20, 20, 20, 20)
 SCINT_PLAN(10000, 10, 10, 10, 10, 10)
+// FP32 only: a row of 16000 or 20000 complex64 fills most of the LDS
+SCINT_PLAN(16000, 40, 40, 40, 10)
+SCINT_PLAN(20000, 40, 40, 10, 10, 5)
 
 // alternatives timed by the tuner (FP32)
 SCINT_PLAN_V(2048, 1, 16, 16, 8, 16)
@@ -82,6 +85,8 @@ SCINT_PLAN_V(8192, 2, 32, 32, 8, 32)
 SCINT_PLAN_V(10000, 1, 20, 20, 20, 5, 5)
 SCINT_PLAN_V(16384, 1, 32, 16, 32, 32)
 SCINT_PLAN_V(16384, 2, 32, 32, 16, 32)
+SCINT_PLAN_V(16000, 1, 20, 20, 20, 20, 2)
+SCINT_PLAN_V(20000, 1, 20, 20, 20, 10, 5)
 
 #undef SCINT_PLAN_EXPAND
 #undef SCINT_PLAN
@@ -89,19 +94,23 @@ SCINT_PLAN_V(16384, 2, 32, 32, 16, 32)
 
 // Number of plan variants of length L (FP32; FP64 uses variant 0 only).
 constexpr int plan_variants(int L) {
-    return (L == 4096 || L == 8192 || L == 16384) ? 3 : (L == 2048 || L == 10000) ? 2 : 1;
+    return (L == 4096 || L == 8192 || L == 16384) ? 3
+           : (L == 2048 || L == 10000 || L == 16000 || L == 20000) ? 2
+                                                                    : 1;
 }
 
 // X(L, V) for every FP32 variant beyond 0
-#define SCINT_VARIANTS_F32(X) X(2048, 1) X(4096, 1) X(4096, 2) X(8192, 1) X(8192, 2) X(10000, 1) X(16384, 1) X(16384, 2)
+#define SCINT_VARIANTS_F32(X) \
+    X(2048, 1) X(4096, 1) X(4096, 2) X(8192, 1) X(8192, 2) X(10000, 1) X(16000, 1) X(16384, 1) X(16384, 2) X(20000, 1)
 
 // Sizes in ascending order, per precision (FP64 stops at 8192 because a
-// 16384-point complex128 row does not fit in the 160 KB of LDS).
+// 10000-point complex128 row does not fit in the 160 KB of LDS; FP32 stops at
+// 20000, whose complex64 row nearly fills it).
 #define SCINT_SIZES_F64(X)                                                      \
     X(16) X(32) X(40) X(64) X(80) X(100) X(128) X(160) X(200) X(256) X(320)     \
     X(400) X(512) X(640) X(1000) X(1024) X(1280) X(2000) X(2048) X(2560)        \
     X(4000) X(4096) X(5000) X(8000) X(8192)
-#define SCINT_SIZES_F32(X) SCINT_SIZES_F64(X) X(10000) X(16384)
+#define SCINT_SIZES_F32(X) SCINT_SIZES_F64(X) X(10000) X(16000) X(16384) X(20000)
 
 // Number of entries of the per-stage twiddle tables of a plan: stage s >= 1
 // holds W_{Ns R}^{r k} for k < Ns and r < R, i.e. Ns R entries.

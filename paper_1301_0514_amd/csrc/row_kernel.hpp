@@ -9,18 +9,26 @@
 
 namespace scint {
 
-// LDS layout of a row: one padding slot every 16 elements breaks the
-// power-of-two strides of the Stockham writes across banks.
+// LDS layout of a row: one padding slot every 32 elements breaks the
+// power-of-two strides of the Stockham writes across banks.  A row whose
+// padded length would not fit the 160 KB of LDS (20000 complex64) takes one
+// slot every 64 elements.
 #ifndef SCINT_LDS_PAD_SHIFT
 #define SCINT_LDS_PAD_SHIFT 5
 #endif
 constexpr int kLdsPadShift = SCINT_LDS_PAD_SHIFT;
-__device__ __forceinline__ int lds_index(int p) { return kLdsPadShift > 0 ? p + (p >> kLdsPadShift) : p; }
+template <int L> constexpr int lds_pad_shift() {
+    return (kLdsPadShift > 0 && (L + (L >> kLdsPadShift)) * 8 > 160 * 1024) ? 6 : kLdsPadShift;
+}
+template <int L> __device__ __forceinline__ int lds_index(int p) {
+    constexpr int sh = lds_pad_shift<L>();
+    return sh > 0 ? p + (p >> sh) : p;
+}
 
 template <typename Real, int L, int V = 0> struct RowCfg {
     using P = Plan<L, V>;
     static constexpr int T = P::T;
-    static constexpr int LDS_STRIDE = kLdsPadShift > 0 ? L + (L >> kLdsPadShift) : L;
+    static constexpr int LDS_STRIDE = lds_pad_shift<L>() > 0 ? L + (L >> lds_pad_shift<L>()) : L;
     static constexpr int ELEM = 2 * (int)sizeof(Real);
     static constexpr int B_THREADS = T >= 256 ? 1 : 256 / T;
     static constexpr int B_LDS = (P::NS > 1) ? ((65536 / (LDS_STRIDE * ELEM)) > 0 ? 65536 / (LDS_STRIDE * ELEM) : 1)
@@ -71,13 +79,13 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<R
         } else {
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_index(base + r * Ns)] = a[r];
+            for (int r = 0; r < R; ++r) lds[lds_index<L>(base + r * Ns)] = a[r];
         }
     }
     if constexpr (!last) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = lds[lds_index(t + m * T)];
+        for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(t + m * T)];
         __syncthreads();
         fft_stage<Real, L, V, s + 1>(v, lds, t, tw);
     }

@@ -28,3 +28,13 @@ def intensity_field(N, seed, n=1):
     """Positive speckle-like intensities (unit exponential), [n, N, N]."""
     rng = np.random.default_rng(seed)
     return rng.exponential(1.0, (n, N, N))
+
+
+def line_phase(N, seed, sigma=3.0, corr=4.0):
+    """One line of Gaussian random phases with a Gaussian correlation of
+    `corr` pixels (periodic), float64 [N]."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(N)
+    k = np.fft.fftfreq(N)
+    f = np.real(np.fft.ifft(np.fft.fft(w) * np.exp(-0.5 * (2 * np.pi * corr * k) ** 2)))
+    return sigma * f / f.std()

@@ -252,3 +252,53 @@ def test_every_plan_variant_vs_oracle(S, oracle, N):
     v, ms = S.plan_variant(N)
     print("N=%d tuner picked plan %d, times %s ms" % (N, v, ms))
     assert 0 <= v < nv and all(t > 0 for t in ms)
+
+
+@pytest.mark.parametrize("N", [8192, 10000, 16000, 16384, 20000])
+def test_separable_screens_every_pixel(S, oracle, N):
+    """phi(x, y) = f(x) + g(y): the oracle's pattern is the outer product of
+    two line propagations, so every pixel of the full-size FP32 pattern is
+    checked, for each compiled plan of the size."""
+    import inputs
+    rho, lam, s = 90.0, 5e-7, 0.9
+    z = 2 * np.pi * rho ** 2 / lam
+    f, g = inputs.line_phase(N, seed=N, sigma=6.0, corr=5.0), inputs.line_phase(N, seed=N + 1, sigma=6.0, corr=5.0)
+    I_ref = np.outer(np.abs(oracle.propagate_line(g, rho, s)) ** 2, np.abs(oracle.propagate_line(f, rho, s)) ** 2)
+    phi = torch.tensor((g[:, None] + f[None, :])[None], dtype=torch.float32, device="cuda")
+    nv = S.num_plan_variants(N)
+    try:
+        for v in range(nv):
+            S.set_plan_variant(N, v)
+            I = host(S.fresnel_propagate(phi, 1.0, lam, z, phase_scale=s))[0]
+            e_rms, e_max = errs(I, I_ref)
+            print("N=%d plan %d e_rms=%.2e e_max=%.2e" % (N, v, e_rms, e_max))
+            assert e_rms < F32_RMS and e_max < F32_MAX
+    finally:
+        S.set_plan_variant(N, -1)
+
+
+@pytest.mark.parametrize("N", [16000, 20000])
+def test_largest_sizes_screen_fresnel_vs_oracle(S, oracle, N):
+    """Screen generation and propagation at the sizes whose rows nearly fill
+    the LDS, against the FP64 oracle at every pixel (R_diff = 4.42 px,
+    R_F = 57.5 px: the paper's 20000^2 configuration).
+
+    With R_diff = 4.42 px the Kolmogorov phase reaches several hundred
+    radians.  The FP32 screen carries about 2^-24 |phi| of rounding per pixel
+    (storage and the inverse FFT), a white phase error that the unitary
+    propagation turns into an intensity error of about twice its size (mean
+    intensity 1).  The RMS bar is therefore max(2e-5, 8 2^-24 phi_rms); the
+    max bar stays at 1e-3."""
+    rho, R, lam = 57.5, 4.42, 2.162e-6
+    z = 2 * np.pi * rho ** 2 / lam
+    I, phi = S.ps_screen_fresnel(N, 1.0, R, 11 / 3, 5, lam, z, want_phi=True)
+    phi_ref = oracle.screen(N, R, 11 / 3, 5, 0)
+    phi_rms = float(np.sqrt(np.mean(phi_ref * phi_ref)))
+    d = host(phi)[0] - phi_ref
+    assert np.sqrt(np.mean(d * d)) < 3e-6 * phi_rms
+    del phi, d
+    I_ref = oracle.propagate(phi_ref, rho)
+    e_rms, e_max = errs(host(I)[0], I_ref)
+    bar = max(F32_RMS, 8 * 2.0 ** -24 * phi_rms)
+    print("N=%d phi_rms=%.1f rad e_rms=%.2e (bar %.2e) e_max=%.2e" % (N, phi_rms, e_rms, bar, e_max))
+    assert e_rms < bar and e_max < F32_MAX
