@@ -74,6 +74,9 @@ def _load():
                 "oracle_modulation_index_region": (c_dbl, [c_int, dp, c_int, c_int, c_int, c_int, dp]),
                 "oracle_light_curves": (None, [c_int, dp, c_int, dp, c_int, c_int, dp, dp]),
                 "oracle_propagate_line": (None, [c_int, c_dbl, c_dbl, dp, dp]),
+                "oracle_ring_spectrum": (None, [c_int, dp, dp, dp]),
+                "oracle_structure_from_spectrum": (c_dbl, [c_int, dp, c_dbl]),
+                "oracle_rdiff_rec": (c_dbl, [c_int, dp]),
                 "oracle_m_theory": (c_dbl, [c_dbl, c_dbl, c_dbl]),
                 "oracle_propagate_vjp": (None, [c_int, c_dbl, c_dbl, dp, dp, dp]),
                 "oracle_propagate_adjoint_field": (None, [c_int, c_dbl, dp, dp]),
@@ -279,6 +282,29 @@ def m_theory(r_diff: float, r_f: float, r_s: float) -> float:
     """Expected m of an extended source, strong quenched regime, Kolmogorov
     (Sect. 4.1, Eq. xparam): (R_diff/R_F)^(1/3) (R_ref/(2 pi R_s))^(7/6)."""
     return _load().oracle_m_theory(r_diff, r_f, r_s)
+
+
+def ring_spectrum(phi):
+    """(S_rec[b], count[b]) for b = 0..N/2: the ring-averaged spectral density
+    |DFT phi|^2 / N^2 of a screen (Sect. 3.1.1), pixel units."""
+    phi = _f64(phi)
+    N = phi.shape[0]
+    S = np.zeros(N // 2 + 1)
+    c = np.zeros(N // 2 + 1)
+    _load().oracle_ring_spectrum(N, _dp(phi), _dp(S), _dp(c))
+    return S, c
+
+
+def structure_from_spectrum(N: int, S, r: float) -> float:
+    """D_rec(r) = 2 (xi(0) - xi(r)) from a ring spectrum (Eq. crec), pixels."""
+    S = _f64(S)
+    return _load().oracle_structure_from_spectrum(N, _dp(S), float(r))
+
+
+def rdiff_rec(N: int, S) -> float:
+    """R_diff^rec (pixels): D_rec(R) = 1, by bisection (NaN if not bracketed)."""
+    S = _f64(S)
+    return _load().oracle_rdiff_rec(N, _dp(S))
 
 
 def propagate_line(phi_1d, rho: float, s: float = 1.0) -> np.ndarray:

@@ -28,6 +28,11 @@
  *                              it, the window's closed-form values, Parseval,
  *                              and the paper's < 1 % flatness for a uniform
  *                              screen
+ *   structure-function check : a single Fourier mode against its closed form
+ *                              through the ring average and J0, the
+ *                              theoretical spectrum's R_diff^rec against a
+ *                              quadrature of the continuous integral, the
+ *                              paper's 540 km
  *   light curves, m theory   : axis-aligned lines equal pattern rows and
  *                              columns, bilinear sampling is exact on linear
  *                              fields and equals the pixels at integer points;
@@ -35,6 +40,7 @@
  *   Propagation at a general rho (N != 2 pi rho^2) beyond the closed forms
  *   above is "parity unpinned" as physics; its algebra is pinned by the DFT.
  */
+#define _DEFAULT_SOURCE /* j0 (Bessel function of the first kind) from libm */
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
@@ -517,6 +523,60 @@ void oracle_fresnel_aperture_direct(int N, double rho, double s, double margin_r
             I_out[(size_t)m * N + mx] = creal(acc) * creal(acc) + cimag(acc) * cimag(acc);
         }
     free(sf);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Structure-function check of a screen (Sect. 3.1.1, Eq. crec), pixel     */
+/* units.  S_rec[b] = <|F_phi|^2>/(L_x L_y) = <|DFT phi|^2>/N^2 over the    */
+/* Fourier pixels of signed frequency k' (components in [-N/2, N/2)) whose  */
+/* |k'| rounds to b, for b = 0 .. N/2; count[b] = number of such pixels.    */
+/* xi(r) = sum_{b=1}^{N/2} 2 pi q_b S_b J0(2 pi q_b r) dq with q_b = b/N and */
+/* dq = 1/N (q_min = 1/N, q_max = 1/2, the paper's integration limits);     */
+/* D(r) = 2 (xi(0) - xi(r)); R_diff^rec solves D = 1.                       */
+/* ------------------------------------------------------------------------ */
+
+void oracle_ring_spectrum(int N, const double *phi, double *S, double *count)
+{
+    size_t NN = (size_t)N * N;
+    cplx *a = (cplx *)malloc(sizeof(cplx) * NN);
+    for (size_t i = 0; i < NN; ++i) a[i] = phi[i];
+    dft2_inplace(N, a, -1);
+    int nb = N / 2 + 1;
+    for (int b = 0; b < nb; ++b) { S[b] = 0.0; count[b] = 0.0; }
+    for (int ky = 0; ky < N; ++ky)
+        for (int kx = 0; kx < N; ++kx) {
+            double fy = signed_freq(ky, N), fx = signed_freq(kx, N);
+            int b = (int)floor(sqrt(fx * fx + fy * fy) + 0.5);
+            if (b >= nb) continue;
+            cplx v = a[(size_t)ky * N + kx];
+            S[b] += (creal(v) * creal(v) + cimag(v) * cimag(v)) / ((double)N * (double)N);
+            count[b] += 1.0;
+        }
+    for (int b = 0; b < nb; ++b)
+        if (count[b] > 0) S[b] /= count[b];
+    free(a);
+}
+
+double oracle_structure_from_spectrum(int N, const double *S, double r)
+{
+    double d = 0.0;
+    for (int b = 1; b <= N / 2; ++b) {
+        double q = (double)b / N;
+        d += 2.0 * ORACLE_PI * q * S[b] * (1.0 - j0(2.0 * ORACLE_PI * q * r)) / N;
+    }
+    return 2.0 * d;
+}
+
+double oracle_rdiff_rec(int N, const double *S)
+{
+    double lo = 1e-3, hi = N / 2.0;
+    if (oracle_structure_from_spectrum(N, S, lo) >= 1.0 || oracle_structure_from_spectrum(N, S, hi) < 1.0)
+        return NAN;
+    for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (oracle_structure_from_spectrum(N, S, mid) < 1.0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
 }
 
 /* ------------------------------------------------------------------------ */
