@@ -381,6 +381,22 @@ def main(argv=None) -> int:
         sec["m_versus_theory_8192"] = {"seconds": t_sweep, "patterns": len(pts), "rows": rows}
         log("m sweep: %d patterns in %.2f s" % (len(pts), t_sweep))
 
+        # structure-function check of a 16000^2 screen (Sect. 3.1.1): the
+        # paper's 540-km configuration (28.85 km pixels, R_diff = 500 km)
+        Ns = 16000
+        phis = scint.ps_generate(Ns, 28.85, 500.0, 11 / 3, 1, 0, 1, torch.float32, device=dev)
+        t0 = time.perf_counter()
+        _, rrec = scint.structure_function(phis, 28.85)
+        t_sf = time.perf_counter() - t0
+        sec["structure_function_16000"] = {"seconds_incl_first_use": t_sf, "rdiff_rec_km": rrec[0],
+                                           "rdiff_input_km": 500.0}
+        t0 = time.perf_counter()
+        scint.structure_function(phis, 28.85)
+        sec["structure_function_16000"]["seconds"] = time.perf_counter() - t0
+        log("structure function 16000^2: R_diff^rec %.1f km (input 500 km), %.3f s" % (
+            rrec[0], sec["structure_function_16000"]["seconds"]))
+        del phis
+
         # forward + adjoint, 16 x 2048^2
         g = presets.GRAD_2048
         nr = presets.GRAD_N_REAL

@@ -238,6 +238,29 @@ int ps_modulation_index_region(int N, const void *I, int n, int x0, int y0, int 
                                int dtype, double *m_out, double *mean_out, void *hip_stream);
 
 /*
+ * ps_structure_function -- the check of a generated screen by its recomputed
+ * structure function (Sect. 3.1.1, Eq. crec).  For each of the n screens:
+ *   S_rec(q_b) = <|F_phi|^2>_ring / (L_x L_y) = delta^2 <|DFT phi|^2>_ring / N^2,
+ * averaged over the Fourier pixels whose signed frequency |k'| (components
+ * in [-N/2, N/2)) rounds to b, q_b = b / (N delta), b = 0 .. N/2;
+ *   xi(r) = sum_{b=1}^{N/2} 2 pi q_b S_rec(q_b) J0(2 pi q_b r) dq, dq = 1/(N delta)
+ * (the paper's limits q_min = 1/(N delta), q_max = 1/(2 delta)),
+ *   D_rec(r) = 2 (xi(0) - xi(r)),
+ * and R_diff^rec, the r with D_rec(r) = 1 (bisection between 1e-3 and N/2
+ * pixels; NaN and a warning if not bracketed).  FP64 ring sums and Hankel
+ * sums (J0 by its power series below 14 and Hankel's expansion above).
+ *   phi        device [n][N][N] real (radians; input, not modified)
+ *   radii      host array of n_r radii >= 0 (length unit of delta), n_r >= 0
+ *   S_out      optional host [n][N/2 + 1]: S_rec in (length unit)^2 rad^2
+ *   D_out      host [n][n_r] (required when n_r > 0): D_rec at the radii
+ *   rdiff_out  optional host [n]: R_diff^rec (length unit of delta)
+ * Synchronises with the stream.
+ */
+int ps_structure_function(int N, double delta, const void *phi, int n, const double *radii,
+                          int n_r, int dtype, double *S_out, double *D_out, double *rdiff_out,
+                          void *hip_stream);
+
+/*
  * ps_light_curves -- light curves as a telescope sweeping the pattern sees
  * them (Sect. 3.3): each pattern is sampled along straight lines at a
  * constant speed.  Pixel (ix, iy) sits at the point (ix, iy) in pixel units;

@@ -49,6 +49,22 @@ struct LineSet {
 hipError_t launch_light_curves(const void *I, int N, int nbatch, const double *lines, int n_lines, int n_samples,
                                int mode, bool f64, void *out, double *stats, hipStream_t stream);
 
+// Ring sums of a power map P [nbatch][N][N] (real): S[b][k] = mean of P over
+// the pixels whose signed frequency |k'| rounds to k, k = 0 .. N/2, in FP64;
+// count[k] = their number (if count != NULL).
+hipError_t launch_ring_sums(const void *P, int N, int nbatch, bool f64, double *S, double *count, hipStream_t stream);
+
+// D(r) = 2 (xi(0) - xi(r)) from ring spectra S [nbatch][N/2 + 1] (pixel units,
+// the J0 sum of Eq. crec) at n_r radii (pixels; by value, kRadiiPerLaunch at a
+// time) into D [nbatch][n_r], and R_diff^rec (D = 1) into rdiff [nbatch] if
+// rdiff != NULL (NaN if not bracketed in [1e-3, N/2]).
+constexpr int kRadiiPerLaunch = 64;
+struct RadiusSet {
+    double r[kRadiiPerLaunch];
+};
+hipError_t launch_hankel(const double *S, int N, int nbatch, const double *radii, int n_r, double *D, double *rdiff,
+                         hipStream_t stream);
+
 // out[b] = scale * sum_blk partials[b * nblk + blk], fixed-order tree.
 hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,
                                 hipStream_t stream);

@@ -360,6 +360,163 @@ hipError_t launch_light_curves(const void *I, int N, int nbatch, const double *l
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------- structure function
+// Ring sums of a power map P [batch][N][N] (either orientation): ring b holds
+// the pixels of signed frequency k' (components in [-N/2, N/2)) with
+// (2b - 1)^2 <= 4 |k'|^2 < (2b + 1)^2 (|k'| rounds to b).  One workgroup per
+// (ring, batch member); each thread walks whole rows of the ring and the
+// partial sums meet in a fixed-order tree, so the result is reproducible.
+__device__ __forceinline__ int64_t isqrt_floor(int64_t v) {  // floor(sqrt(v)), v >= 0
+    int64_t r = (int64_t)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void ring_sum_kernel(const Real *__restrict__ P, int N, double *S, double *count) {
+    __shared__ double red[256];
+    const int b = blockIdx.x, bat = blockIdx.y;
+    const Real *img = P + (int64_t)bat * N * N;
+    const int64_t lo2 = b == 0 ? 0 : (int64_t)(2 * b - 1) * (2 * b - 1), hi2 = (int64_t)(2 * b + 1) * (2 * b + 1);
+    const int h = N / 2;
+    double acc = 0.0, cnt = 0.0;
+    for (int ky = -(b + 1) + (int)threadIdx.x; ky <= b + 1; ky += 256) {
+        if (ky < -h || ky >= h) continue;
+        const int64_t t = 4 * (int64_t)ky * ky;
+        if (t >= hi2) continue;
+        // kx >= 0 with lo2 <= 4 kx^2 + t < hi2
+        const int64_t kmin = (lo2 - t <= 0) ? 0 : isqrt_floor((lo2 - t + 3) / 4 - 1) + 1;
+        const int64_t kmax = isqrt_floor((hi2 - t - 1) / 4);
+        const Real *row = img + (int64_t)(ky < 0 ? ky + N : ky) * N;
+        for (int64_t kx = kmin; kx <= kmax; ++kx) {
+            if (kx < h) {  // +kx
+                acc += (double)row[kx];
+                cnt += 1.0;
+            }
+            if (kx > 0 && kx <= h) {  // -kx
+                acc += (double)row[N - kx];
+                cnt += 1.0;
+            }
+        }
+    }
+    const double tot = block_tree_sum(acc, red);
+    __syncthreads();
+    const double c = block_tree_sum(cnt, red);
+    if (threadIdx.x == 0) {
+        S[(int64_t)bat * gridDim.x + b] = c > 0 ? tot / c : 0.0;
+        if (count && bat == 0) count[b] = c;
+    }
+}
+
+hipError_t launch_ring_sums(const void *P, int N, int nbatch, bool f64, double *S, double *count, hipStream_t stream) {
+    dim3 grid(N / 2 + 1, nbatch);
+    if (f64)
+        hipLaunchKernelGGL((ring_sum_kernel<double>), grid, dim3(256), 0, stream, static_cast<const double *>(P), N, S,
+                           count);
+    else
+        hipLaunchKernelGGL((ring_sum_kernel<float>), grid, dim3(256), 0, stream, static_cast<const float *>(P), N, S,
+                           count);
+    return hipGetLastError();
+}
+
+// J0, the Bessel function of the first kind of order 0, in FP64: its power
+// series sum_k (-x^2/4)^k / (k!)^2 below x = 14 (largest term about 1e4, so
+// an absolute error near 1e-12), and above it Hankel's asymptotic expansion
+// J0 = sqrt(2 / (pi x)) (P cos(x - pi/4) - Q sin(x - pi/4)),
+// P = sum_k (-1)^k a_2k / x^2k, Q = sum_k (-1)^k a_(2k+1) / x^(2k+1),
+// a_k = prod_{j <= k} (2j - 1)^2 / (k! 8^k), summed while the terms shrink.
+__device__ double bessel_j0(double x) {
+    x = fabs(x);
+    if (x < 14.0) {
+        const double y = 0.25 * x * x;
+        double t = 1.0, sum = 1.0;
+        for (int k = 1; k < 80; ++k) {
+            t *= -y / ((double)k * (double)k);
+            sum += t;
+            if (fabs(t) < 1e-17 * fabs(sum) && (double)k * k > y) break;
+        }
+        return sum;
+    }
+    double P = 1.0, Q = 0.0, a = 1.0, xp = 1.0, last = 1.0;
+    for (int k = 1; k < 60; ++k) {
+        a *= (double)((2 * k - 1) * (2 * k - 1)) / (8.0 * k);
+        xp *= x;
+        const double term = a / xp;
+        if (term > last) break;  // the asymptotic series starts to diverge
+        last = term;
+        if (k & 1)
+            Q += ((k / 2) & 1) ? term : -term;  // k = 1: -a1/x, k = 3: +a3/x^3, ...
+        else
+            P += ((k / 2) & 1) ? -term : term;  // k = 2: -a2/x^2, k = 4: +a4/x^4, ...
+        if (term < 1e-17) break;
+    }
+    const double ph = x - 0.25 * 3.14159265358979323846;
+    return sqrt(2.0 / (3.14159265358979323846 * x)) * (P * cos(ph) - Q * sin(ph));
+}
+
+// D(r) = 2 sum_{b=1}^{N/2} 2 pi (b/N) S_b (1 - J0(2 pi b r / N)) / N for the
+// workgroup's ring spectrum S (pixel units), summed over the block.
+__device__ double structure_at(const double *S, int N, double r, double *red) {
+    double acc = 0.0;
+    for (int b = 1 + (int)threadIdx.x; b <= N / 2; b += 256) {
+        const double q = (double)b / N;
+        acc += q * S[b] * (1.0 - bessel_j0(2.0 * 3.14159265358979323846 * q * r));
+    }
+    __syncthreads();
+    const double tot = block_tree_sum(acc, red);
+    return 4.0 * 3.14159265358979323846 * tot / N;
+}
+
+// One workgroup per screen: D at the given radii (pixels) and, if rdiff !=
+// NULL, R_diff^rec solving D = 1 by bisection on [1e-3, N/2] (NaN when the
+// root is not bracketed).
+__global__ __launch_bounds__(256) void hankel_kernel(const double *S, int N, RadiusSet rs, int n_r, double *D,
+                                                     int ld_D, int r0, double *rdiff) {
+    __shared__ double red[256];
+    const int bat = blockIdx.x;
+    const double *Sb = S + (int64_t)bat * (N / 2 + 1);
+    for (int j = 0; j < n_r; ++j) {
+        const double d = structure_at(Sb, N, rs.r[j], red);
+        if (threadIdx.x == 0) D[(int64_t)bat * ld_D + r0 + j] = d;
+    }
+    if (!rdiff) return;
+    double lo = 1e-3, hi = 0.5 * N;
+    const double dlo = structure_at(Sb, N, lo, red), dhi = structure_at(Sb, N, hi, red);
+    if (!(dlo < 1.0 && dhi >= 1.0)) {
+        if (threadIdx.x == 0) rdiff[bat] = __longlong_as_double(0x7ff8000000000000LL);
+        return;
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {  // every thread sees the same lo, hi
+        const double mid = 0.5 * (lo + hi);
+        if (structure_at(Sb, N, mid, red) < 1.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    if (threadIdx.x == 0) rdiff[bat] = 0.5 * (lo + hi);
+}
+
+hipError_t launch_hankel(const double *S, int N, int nbatch, const double *radii, int n_r, double *D, double *rdiff,
+                         hipStream_t stream) {
+    if (n_r == 0) {
+        RadiusSet rs{};
+        hipLaunchKernelGGL(hankel_kernel, dim3(nbatch), dim3(256), 0, stream, S, N, rs, 0, D, 0, 0, rdiff);
+        return hipGetLastError();
+    }
+    for (int j0 = 0; j0 < n_r; j0 += kRadiiPerLaunch) {
+        const int nr = n_r - j0 < kRadiiPerLaunch ? n_r - j0 : kRadiiPerLaunch;
+        RadiusSet rs{};
+        for (int j = 0; j < nr; ++j) rs.r[j] = radii[j0 + j];
+        // the root is found once, with the first chunk of radii
+        hipLaunchKernelGGL(hankel_kernel, dim3(nbatch), dim3(256), 0, stream, S, N, rs, nr, D, n_r, j0,
+                           j0 == 0 ? rdiff : nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 __global__ __launch_bounds__(256) void finalize_kernel(const double *partials, int nblk, double scale, double *out) {
     __shared__ double red[256];
     const int b = blockIdx.x;

@@ -1311,6 +1311,66 @@ int ps_m_theory(double r_diff, double r_f, double r_s, double *m_out) {
     return PS_OK;
 }
 
+int ps_structure_function(int N, double delta, const void *phi, int n, const double *radii, int n_r, int dtype,
+                          double *S_out, double *D_out, double *rdiff_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi) return fail(PS_E_NULL, "phi is NULL");
+    if (int rc = check_aligned({phi})) return rc;
+    if (!finite_pos(delta)) return fail(PS_E_PARAM, "delta must be finite and > 0");
+    if (n_r < 0 || (n_r > 0 && (!radii || !D_out))) return fail(PS_E_PARAM, "n_r >= 0, with radii and D_out when > 0");
+    for (int j = 0; j < n_r; ++j)
+        if (!(std::isfinite(radii[j]) && radii[j] >= 0.0)) return fail(PS_E_PARAM, "radii must be finite and >= 0");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int nbins = N / 2 + 1;
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    std::vector<double> rpx(n_r);
+    for (int j = 0; j < n_r; ++j) rpx[j] = radii[j] / delta;
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        const size_t small = (size_t)nb * nbins * 8 + (size_t)nb * std::max(n_r, 1) * 8 + (size_t)nb * 8 + 1024;
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + small, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        double *S = reinterpret_cast<double *>(base + c.take((size_t)nb * nbins * 8));
+        double *D = reinterpret_cast<double *>(base + c.take((size_t)nb * std::max(n_r, 1) * 8));
+        double *R = reinterpret_cast<double *>(base + c.take((size_t)nb * 8));
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        // |DFT phi|^2 / N^2: DFT along x, transpose, DFT along y and |.|^2
+        ProgBuilder a(N, (int64_t)nb * N);
+        a.op(ROP_LOAD_R, ph, nn(N), N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, nn(N), N);
+        if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
+        ProgBuilder d(N, (int64_t)nb * N);
+        d.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0 / ((double)N * (double)N))
+            .op(ROP_STORE_ACC, W1, nn(N), N);
+        if (int rc = run_row<ProgAbs2Tag>(dtype, N, d.p, d.n, stream)) return rc;
+        HIP_TRY(launch_ring_sums(W1, N, nb, dtype == PS_F64, S, nullptr, stream));
+        if (n_r > 0 || rdiff_out)
+            HIP_TRY(launch_hankel(S, N, nb, rpx.data(), n_r, D, rdiff_out ? R : nullptr, stream));
+        std::vector<double> hS(S_out ? (size_t)nb * nbins : 0), hD((size_t)nb * n_r), hR(rdiff_out ? nb : 0);
+        if (S_out) HIP_TRY(hipMemcpyAsync(hS.data(), S, hS.size() * 8, hipMemcpyDeviceToHost, stream));
+        if (n_r > 0) HIP_TRY(hipMemcpyAsync(hD.data(), D, hD.size() * 8, hipMemcpyDeviceToHost, stream));
+        if (rdiff_out) HIP_TRY(hipMemcpyAsync(hR.data(), R, hR.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        // physical units: S in (length unit)^2 rad^2, R_diff^rec in the length unit
+        for (size_t i = 0; i < hS.size(); ++i) S_out[(size_t)b0 * nbins + i] = hS[i] * delta * delta;
+        for (size_t i = 0; i < hD.size(); ++i) D_out[(size_t)b0 * n_r + i] = hD[i];
+        for (int i = 0; i < (int)hR.size(); ++i) {
+            rdiff_out[b0 + i] = hR[i] * delta;
+            if (!std::isfinite(hR[i])) g_last_warning = "D_rec = 1 is not reached between 1e-3 and N/2 pixels";
+        }
+    }
+    return PS_OK;
+}
+
 int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype, void *grad_out, double *loss_out,
                void *hip_stream) {
     g_last_error.clear();

@@ -48,6 +48,7 @@ SIGNATURES = {
                                             _vp]),
     "ps_light_curves": (_c_int, [_c_int, _vp, _c_int, _dp, _c_int, _c_int, _c_int, _c_int, _vp, _dp, _vp]),
     "ps_m_theory": (_c_int, [_c_dbl, _c_dbl, _c_dbl, _dp]),
+    "ps_structure_function": (_c_int, [_c_int, _c_dbl, _vp, _c_int, _dp, _c_int, _c_int, _dp, _dp, _dp, _vp]),
     "ps_l2_loss": (_c_int, [_c_int, _vp, _vp, _c_int, _c_int, _vp, _dp, _vp]),
     "ps_last_error": (ctypes.c_char_p, []),
     "ps_last_warning": (ctypes.c_char_p, []),
@@ -352,6 +353,27 @@ def light_curves(I: torch.Tensor, lines, n_samples: int, mode: int = 0, want_m: 
     if not want_m:
         return curves
     return curves, [[m[b * n_lines + l] for l in range(n_lines)] for b in range(n)]
+
+
+def structure_function(phi: torch.Tensor, delta, radii=(), want_spectrum=False):
+    """Recomputed structure function of each screen (Sect. 3.1.1, Eq. crec):
+    returns (D [n][len(radii)], R_diff^rec [n]) and, if asked, the ring
+    spectrum S_rec [n][N/2 + 1] (q_b = b / (N delta)); synchronises."""
+    N = phi.shape[-1]
+    n = _batch_of(phi, N)
+    nr = len(radii)
+    r = (ctypes.c_double * max(nr, 1))(*[float(v) for v in radii])
+    D = (ctypes.c_double * max(n * nr, 1))()
+    R = (ctypes.c_double * n)()
+    S = (ctypes.c_double * (n * (N // 2 + 1)))() if want_spectrum else None
+    rc = load_library().ps_structure_function(int(N), float(delta), _ptr(phi), n, r if nr else None, nr,
+                                              _dtype_code(phi.dtype), S, D if nr else None, R, _stream(phi.device))
+    _check("ps_structure_function", rc)
+    Ds = [[D[b * nr + j] for j in range(nr)] for b in range(n)]
+    Rs = [R[b] for b in range(n)]
+    if want_spectrum:
+        return Ds, Rs, [[S[b * (N // 2 + 1) + k] for k in range(N // 2 + 1)] for b in range(n)]
+    return Ds, Rs
 
 
 def m_theory(r_diff, r_f, r_s) -> float:
