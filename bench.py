@@ -397,6 +397,22 @@ def main(argv=None) -> int:
             rrec[0], sec["structure_function_16000"]["seconds"]))
         del phis
 
+        # the paper's scale: one 20000^2 screen through the 21-wavelength K_s
+        # band (Sect. 3.2.4)
+        kc = presets.PAPER_KS_20000
+        phik = scint.ps_generate(kc.N, kc.delta, kc.r_diff, 11 / 3, kc.seed, 0, 1, torch.float32, device=dev)
+        Ik = torch.empty_like(phik)
+
+        def ks_band():
+            scint.illumination_polychromatic(phik, kc.delta, kc.z, kc.lam_ref, kc.lambdas(), out=Ik)
+
+        tk = timed(ks_band, 2)
+        sec["paper_ks_20000_21_lambda"] = {"ms_per_call": tk,
+                                           "pt_per_s": kc.N ** 2 * kc.n_lambda / (tk / 1e3),
+                                           "m": scint.ps_modulation_index(Ik)[0]}
+        log("K_s band 20000^2 x 21 lambda: %.1f ms, m = %.3f" % (tk, sec["paper_ks_20000_21_lambda"]["m"]))
+        del phik, Ik
+
         # forward + adjoint, 16 x 2048^2
         g = presets.GRAD_2048
         nr = presets.GRAD_N_REAL

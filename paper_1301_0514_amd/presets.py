@@ -66,3 +66,30 @@ POLY_8192 = Poly()
 GRAD_2048 = Mono(N=2048, rho=48.0, R=24.0, lam=500e-9, seeds=(1,))
 GRAD_N_REAL = 16
 GRAD_TARGET_SEED0 = 1000
+
+
+# The paper's own scale (Sect. 3.2.4, Figs. pattern and multypoint): 20000^2
+# pixels of 22.6 km, R_diff = 100 km at 2.16 um, screen at 160 pc (R_F = 1300 km
+# = 57.5 px, R_diff = 4.42 px), the K_s passband as 21 wavelengths regularly
+# spaced in [2.08, 2.28] um with equal weights.
+PC_M = 3.0856775814913673e16
+
+
+@dataclass(frozen=True)
+class KsBand:
+    N: int = 20000
+    delta: float = 22.6e3  # m
+    r_diff: float = 100e3  # m, at lam_ref
+    z: float = 160 * PC_M  # m
+    lam_ref: float = 2.16e-6
+    band: tuple = (2.08e-6, 2.28e-6)
+    n_lambda: int = 21
+    seed: int = 1
+
+    def lambdas(self, n=None):
+        n = self.n_lambda if n is None else n
+        lo, hi = self.band
+        return [0.5 * (lo + hi)] if n == 1 else [lo + (hi - lo) * j / (n - 1) for j in range(n)]
+
+
+PAPER_KS_20000 = KsBand()

@@ -302,3 +302,47 @@ def test_largest_sizes_screen_fresnel_vs_oracle(S, oracle, N):
     bar = max(F32_RMS, 8 * 2.0 ** -24 * phi_rms)
     print("N=%d phi_rms=%.1f rad e_rms=%.2e (bar %.2e) e_max=%.2e" % (N, phi_rms, e_rms, bar, e_max))
     assert e_rms < bar and e_max < F32_MAX
+
+
+def test_paper_ks_band_20000(S, P):
+    """The paper's scale (Sect. 3.2.4): one 20000^2 screen seen through the
+    K_s band.  The point-source pattern is in the strong regime (m ~ 1); the
+    co-added pattern's m falls as components are added and is within 3 % of
+    its 21-component value at ten components ("about ten suffice"), near the
+    paper's ~55 %."""
+    from tests._golden import paper_values
+    pv = paper_values()
+    c = P.PAPER_KS_20000
+    assert c.N == pv["ks_pixels"] and c.n_lambda == pv["ks_n_lambda"]
+    phi = S.ps_generate(c.N, c.delta, c.r_diff, 11 / 3, c.seed, 0, 1, torch.float32)
+    m_mono = S.ps_modulation_index(S.fresnel_propagate(phi, c.delta, c.lam_ref, c.z))[0]
+    ms = {}
+    for n in (1, 2, 3, 5, 7, 10, 14, 21):
+        ms[n] = S.ps_modulation_index(S.illumination_polychromatic(phi, c.delta, c.z, c.lam_ref, c.lambdas(n)))[0]
+    print("K_s 20000^2: m mono %.4f, m(n) %s" % (m_mono, {k: round(v, 4) for k, v in ms.items()}))
+    assert 0.9 < m_mono < 1.2
+    ns = sorted(ms)
+    assert all(ms[a] >= ms[b] - 2e-3 for a, b in zip(ns, ns[1:]))
+    n10 = int(pv["ks_components_enough"])
+    assert abs(ms[n10] / ms[21] - 1) < 0.03
+    assert ms[21] == pytest.approx(pv["m_ks_point"], rel=0.2)
+
+
+def test_ks_band_20000_every_pixel_vs_oracle(S, P, oracle):
+    """illumination_polychromatic at 20000^2 with the 21 K_s wavelengths (three
+    wavelength chunks) on a separable screen: each wavelength's oracle pattern
+    is an outer product of two line propagations, so the co-added pattern is
+    one matrix product and every pixel is checked."""
+    import inputs
+    c = P.PAPER_KS_20000
+    N, lams = c.N, c.lambdas()
+    rho_of = lambda lam: np.sqrt(lam * c.z / (2 * np.pi)) / c.delta
+    f, g = inputs.line_phase(N, seed=3, sigma=40.0, corr=6.0), inputs.line_phase(N, seed=4, sigma=40.0, corr=6.0)
+    F = np.stack([np.abs(oracle.propagate_line(f, rho_of(l), c.lam_ref / l)) ** 2 for l in lams])  # [n_l, N]
+    G = np.stack([np.abs(oracle.propagate_line(g, rho_of(l), c.lam_ref / l)) ** 2 for l in lams])
+    I_ref = (G.T @ F) / len(lams)  # [y, x]
+    phi = torch.tensor((g[:, None] + f[None, :])[None], dtype=torch.float32, device="cuda")
+    I = host(S.illumination_polychromatic(phi, c.delta, c.z, c.lam_ref, lams))[0]
+    e_rms, e_max = errs(I, I_ref)
+    print("K_s 20000^2 separable: e_rms=%.2e e_max=%.2e" % (e_rms, e_max))
+    assert e_rms < F32_RMS and e_max < F32_MAX
