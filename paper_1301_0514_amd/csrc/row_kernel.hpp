@@ -50,6 +50,50 @@ template <typename Real, int L, int V = 0> struct RowCfg {
 };
 
 // ---------------------------------------------------------------- FFT
+// a[r] *= W^r for r = 1 .. R-1, where w[r] = W^r is the stage's (correctly
+// rounded) table row.  Loading all R-1 entries from the cached table stalls
+// every stage on its latency, so only a few are loaded and the rest formed as
+// products no more than three multiplications deep: within a group of G
+// (8, 5 or 4) consecutive powers, W^1, W^2 (and W^4 for G = 8) are loaded and
+// W^3 = W^1 W^2, W^5 = W^1 W^4, W^6 = W^2 W^4, W^7 = W^3 W^4 (W^4 = W^2 W^2 for
+// G = 5); across groups W^(gG + b) = W^(gG) W^b with W^(gG) loaded.
+template <int R> constexpr int twiddle_group() {
+    return (R % 8 == 0) ? 8 : (R % 5 == 0) ? 5 : (R % 4 == 0) ? 4 : R;
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ void apply_twiddles(cpx<Real> (&a)[R], const cpx<Real> *__restrict__ w) {
+    constexpr int G = twiddle_group<R>();
+    cpx<Real> p[G];
+    p[0] = {(Real)1, (Real)0};
+    if constexpr (G == 8) {
+        p[1] = w[1];
+        p[2] = w[2];
+        p[4] = w[4];
+        p[3] = cmul(p[1], p[2]);
+        p[5] = cmul(p[1], p[4]);
+        p[6] = cmul(p[2], p[4]);
+        p[7] = cmul(p[3], p[4]);
+    } else if constexpr (G == 5) {
+        p[1] = w[1];
+        p[2] = w[2];
+        p[3] = cmul(p[1], p[2]);
+        p[4] = cmul(p[2], p[2]);
+    } else {
+#pragma unroll
+        for (int b = 1; b < G; ++b) p[b] = w[b];
+    }
+#pragma unroll
+    for (int b = 1; b < G; ++b) a[b] = cmul(a[b], p[b]);
+#pragma unroll
+    for (int g = 1; g < R / G; ++g) {
+        const cpx<Real> base = w[g * G];
+        a[g * G] = cmul(a[g * G], base);
+#pragma unroll
+        for (int b = 1; b < G; ++b) a[g * G + b] = cmul(a[g * G + b], cmul(base, p[b]));
+    }
+}
+
 template <typename Real, int L, int V, int s>
 __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
                                           const cpx<Real> *__restrict__ tw) {
@@ -68,9 +112,7 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<R
             // keep the compiler from hoisting twiddle loads out of loops over
             // wavelengths (they would stay live in registers across FFTs)
             asm volatile("" ::: "memory");
-            const cpx<Real> *w = tw + twiddle_offset<L, V>(s) + k * R;
-#pragma unroll
-            for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
+            apply_twiddles<Real, R>(a, tw + twiddle_offset<L, V>(s) + k * R);
         }
         Dft<R, -1, Real>::run(a);
         if constexpr (last) {
