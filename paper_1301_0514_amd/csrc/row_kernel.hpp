@@ -25,6 +25,76 @@ template <int L> __device__ __forceinline__ int lds_index(int p) {
     return sh > 0 ? p + (p >> sh) : p;
 }
 
+// ---------------------------------------------------------------- twiddles
+// a[r] *= W^r (r = 1 .. R-1) uses only a few table entries: within a group of
+// G (8, 5 or 4) consecutive powers W^1, W^2 (and W^4 for G = 8) are loaded
+// and W^3 = W^1 W^2, W^5 = W^1 W^4, W^6 = W^2 W^4, W^7 = W^3 W^4 formed (W^4 =
+// W^2 W^2 for G = 5); across groups W^(gG + b) = W^(gG) W^b with W^(gG)
+// loaded -- every twiddle within three multiplications of table values.
+template <int R> constexpr int twiddle_group() {
+    return (R % 8 == 0) ? 8 : (R % 5 == 0) ? 5 : (R % 4 == 0) ? 4 : R;
+}
+template <int R> constexpr int tw_nbase() {
+    constexpr int G = twiddle_group<R>();
+    return (G == 8 ? 3 : G == 5 ? 2 : G - 1) + (R / G - 1);
+}
+// power of W held in base slot b
+template <int R> constexpr int tw_base_power(int b) {
+    constexpr int G = twiddle_group<R>();
+    constexpr int nin = G == 8 ? 3 : G == 5 ? 2 : G - 1;
+    if (b < nin) return G == 8 ? (1 << b) : b + 1;
+    return (b - nin + 1) * G;
+}
+
+// Twiddle cache.  Butterfly j = t + i T of stage s uses W_{Ns R}^{r k},
+// k = j mod Ns.  If T is a multiple of Ns, k = t mod Ns for every i (mode 1);
+// if Ns is a multiple of T, k = t + (i mod Ns/T) T and W^{r k} =
+// W^{r t} W^{r (i mod Ns/T) T}, the second factor a compile-time constant
+// (mode 2).  Either way a thread's base twiddles depend on t alone, so each
+// workgroup copies them to LDS once per launch; other stages (mode 0) read
+// the table in global memory.
+template <int L, int V> constexpr int tw_mode(int s) {
+    using P = Plan<L, V>;
+    const int Ns = stage_ns<L, V>(s);
+    if (s == 0 || Ns == 1) return 0;
+    if (P::T % Ns == 0) return 1;
+    if (Ns % P::T == 0) return 2;
+    return 0;
+}
+template <int L, int V> constexpr int tw_cache_count(int s) {
+    const int m = tw_mode<L, V>(s);
+    return m == 1 ? stage_ns<L, V>(s) : m == 2 ? Plan<L, V>::T : 0;
+}
+template <int L, int V> constexpr int tw_nbase_at(int s) {
+    constexpr int NS = Plan<L, V>::NS;
+    int n = 0;
+    for (int q = 0; q < NS; ++q)
+        if (q == s) {
+            const int R = Plan<L, V>::R[q];
+            const int G = (R % 8 == 0) ? 8 : (R % 5 == 0) ? 5 : (R % 4 == 0) ? 4 : R;
+            n = (G == 8 ? 3 : G == 5 ? 2 : G - 1) + (R / G - 1);
+        }
+    return n;
+}
+template <int L, int V> constexpr int tw_cache_offset(int s) {
+    int off = 0;
+    for (int q = 1; q < s; ++q) off += tw_cache_count<L, V>(q) * tw_nbase_at<L, V>(q);
+    return off;
+}
+template <int L, int V> constexpr int tw_cache_entries() { return tw_cache_offset<L, V>(Plan<L, V>::NS); }
+
+// exp(-2 pi i r c / M) for r < R, at compile time
+template <int R, long long C, long long M> struct TwConst {
+    double c[R], s[R];
+    constexpr TwConst() : c(), s() {
+        for (int r = 0; r < R; ++r) {
+            SinCos v = sincos2pi(-(long long)r * C, M);
+            c[r] = v.c;
+            s[r] = v.s;
+        }
+    }
+};
+
 template <typename Real, int L, int V = 0> struct RowCfg {
     using P = Plan<L, V>;
     static constexpr int T = P::T;
@@ -35,11 +105,17 @@ template <typename Real, int L, int V = 0> struct RowCfg {
                                              : B_THREADS;
     static constexpr int B = B_THREADS < B_LDS ? B_THREADS : B_LDS;  // rows per workgroup
     static constexpr int THREADS = T * B;
-    // LDS: the FFT exchange buffers, or at least one double per thread for
-    // the row reductions.
+    // LDS: the FFT exchange buffers, then the twiddle cache when it fits (two
+    // workgroups per CU kept where the rows allowed two), or at least one
+    // double per thread for the row reductions.
     static constexpr int FFT_LDS_BYTES = (P::NS > 1) ? B * LDS_STRIDE * ELEM : 0;
+    static constexpr int TWC_BYTES = tw_cache_entries<L, V>() * ELEM;
+    static constexpr bool TWC_ON =
+        TWC_BYTES > 0 && (FFT_LDS_BYTES <= 80 * 1024 ? FFT_LDS_BYTES + TWC_BYTES <= 80 * 1024
+                                                     : FFT_LDS_BYTES + TWC_BYTES <= 160 * 1024);
     static constexpr int RED_LDS_BYTES = THREADS * 8;
-    static constexpr int LDS_BYTES = FFT_LDS_BYTES > RED_LDS_BYTES ? FFT_LDS_BYTES : RED_LDS_BYTES;
+    static constexpr int USED_BYTES = FFT_LDS_BYTES + (TWC_ON ? TWC_BYTES : 0);
+    static constexpr int LDS_BYTES = USED_BYTES > RED_LDS_BYTES ? USED_BYTES : RED_LDS_BYTES;
     // lower bound on the occupancy the register allocator must keep: two
     // waves per SIMD (up to 256 VGPRs), which the heaviest programs need
     // without spilling; lighter programs use fewer registers anyway
@@ -50,69 +126,122 @@ template <typename Real, int L, int V = 0> struct RowCfg {
 };
 
 // ---------------------------------------------------------------- FFT
-// a[r] *= W^r for r = 1 .. R-1, where w[r] = W^r is the stage's (correctly
-// rounded) table row.  Loading all R-1 entries from the cached table stalls
-// every stage on its latency, so only a few are loaded and the rest formed as
-// products no more than three multiplications deep: within a group of G
-// (8, 5 or 4) consecutive powers, W^1, W^2 (and W^4 for G = 8) are loaded and
-// W^3 = W^1 W^2, W^5 = W^1 W^4, W^6 = W^2 W^4, W^7 = W^3 W^4 (W^4 = W^2 W^2 for
-// G = 5); across groups W^(gG + b) = W^(gG) W^b with W^(gG) loaded.
-template <int R> constexpr int twiddle_group() {
-    return (R % 8 == 0) ? 8 : (R % 5 == 0) ? 5 : (R % 4 == 0) ? 4 : R;
+// the group powers p[b] = W^b (b < G) from the base values (slots as in
+// tw_base_power), and the twiddle of power r
+template <typename Real, int R> struct TwGroup {
+    static constexpr int G = twiddle_group<R>();
+    static constexpr int NIN = G == 8 ? 3 : G == 5 ? 2 : G - 1;
+    cpx<Real> p[G];
+    cpx<Real> base[R / G];
+    __device__ __forceinline__ void build(const cpx<Real> *bv) {
+        p[0] = {(Real)1, (Real)0};
+        if constexpr (G == 8) {
+            p[1] = bv[0];
+            p[2] = bv[1];
+            p[4] = bv[2];
+            p[3] = cmul(p[1], p[2]);
+            p[5] = cmul(p[1], p[4]);
+            p[6] = cmul(p[2], p[4]);
+            p[7] = cmul(p[3], p[4]);
+        } else if constexpr (G == 5) {
+            p[1] = bv[0];
+            p[2] = bv[1];
+            p[3] = cmul(p[1], p[2]);
+            p[4] = cmul(p[2], p[2]);
+        } else {
+#pragma unroll
+            for (int b = 1; b < G; ++b) p[b] = bv[b - 1];
+        }
+        base[0] = {(Real)1, (Real)0};
+#pragma unroll
+        for (int g = 1; g < R / G; ++g) base[g] = bv[NIN + g - 1];
+    }
+    __device__ __forceinline__ cpx<Real> w(int r) const {
+        const int g = r / G, b = r % G;
+        return g == 0 ? p[b] : (b == 0 ? base[g] : cmul(base[g], p[b]));
+    }
+};
+
+// a[r] *= W^r (r >= 1) with the base values bv[] of the butterfly's k; for
+// mode 2 butterflies past the first block of T, also by the constant
+// W_M^{r c} (M = Ns R, c = (i mod Ns/T) T)
+template <typename Real, int R, long long C, long long M>
+__device__ __forceinline__ void apply_twiddles(cpx<Real> (&a)[R], const TwGroup<Real, R> &tg) {
+    if constexpr (C == 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], tg.w(r));
+    } else {
+        constexpr TwConst<R, C, M> K{};
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], cmul(tg.w(r), cpx<Real>{(Real)K.c[r], (Real)K.s[r]}));
+    }
 }
 
-template <typename Real, int R>
-__device__ __forceinline__ void apply_twiddles(cpx<Real> (&a)[R], const cpx<Real> *__restrict__ w) {
-    constexpr int G = twiddle_group<R>();
-    cpx<Real> p[G];
-    p[0] = {(Real)1, (Real)0};
-    if constexpr (G == 8) {
-        p[1] = w[1];
-        p[2] = w[2];
-        p[4] = w[4];
-        p[3] = cmul(p[1], p[2]);
-        p[5] = cmul(p[1], p[4]);
-        p[6] = cmul(p[2], p[4]);
-        p[7] = cmul(p[3], p[4]);
-    } else if constexpr (G == 5) {
-        p[1] = w[1];
-        p[2] = w[2];
-        p[3] = cmul(p[1], p[2]);
-        p[4] = cmul(p[2], p[2]);
-    } else {
+template <typename Real, int R> __device__ __forceinline__ void load_bases(cpx<Real> *bv, const cpx<Real> *w) {
 #pragma unroll
-        for (int b = 1; b < G; ++b) p[b] = w[b];
-    }
-#pragma unroll
-    for (int b = 1; b < G; ++b) a[b] = cmul(a[b], p[b]);
-#pragma unroll
-    for (int g = 1; g < R / G; ++g) {
-        const cpx<Real> base = w[g * G];
-        a[g * G] = cmul(a[g * G], base);
-#pragma unroll
-        for (int b = 1; b < G; ++b) a[g * G + b] = cmul(a[g * G + b], cmul(base, p[b]));
-    }
+    for (int b = 0; b < tw_nbase<R>(); ++b) bv[b] = w[tw_base_power<R>(b)];
 }
+
+template <typename Real, int L, int V, int s, int i = 0>
+__device__ __forceinline__ void stage_butterflies(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
+                                                  const cpx<Real> *__restrict__ tw, const cpx<Real> *twc,
+                                                  TwGroup<Real, Plan<L, V>::R[s]> &tg);
 
 template <typename Real, int L, int V, int s>
 __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
-                                          const cpx<Real> *__restrict__ tw) {
+                                          const cpx<Real> *__restrict__ tw, const cpx<Real> *twc) {
+    using P = Plan<L, V>;
+    constexpr int E = P::E, T = P::T, R = P::R[s];
+    constexpr int Ns = stage_ns<L, V>(s);
+    constexpr int mode = tw_mode<L, V>(s);
+    constexpr bool last = (s == P::NS - 1);
+    TwGroup<Real, R> tg;
+    if constexpr (mode != 0 && RowCfg<Real, L, V>::TWC_ON) {
+        // the thread's base twiddles, once for all its butterflies of the stage
+        cpx<Real> bv[tw_nbase<R>()];
+        const cpx<Real> *src = twc + tw_cache_offset<L, V>(s) + (mode == 1 ? t % Ns : t) * tw_nbase<R>();
+#pragma unroll
+        for (int b = 0; b < tw_nbase<R>(); ++b) bv[b] = src[b];
+        tg.build(bv);
+    }
+    stage_butterflies<Real, L, V, s, 0>(v, lds, t, tw, twc, tg);
+    if constexpr (!last) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(t + m * T)];
+        __syncthreads();
+        fft_stage<Real, L, V, s + 1>(v, lds, t, tw, twc);
+    }
+}
+
+template <typename Real, int L, int V, int s, int i>
+__device__ __forceinline__ void stage_butterflies(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
+                                                  const cpx<Real> *__restrict__ tw, const cpx<Real> *twc,
+                                                  TwGroup<Real, Plan<L, V>::R[s]> &tg) {
     using P = Plan<L, V>;
     constexpr int E = P::E, T = P::T, R = P::R[s], Q = E / R;
     constexpr int Ns = stage_ns<L, V>(s);
+    constexpr int mode = tw_mode<L, V>(s);
     constexpr bool last = (s == P::NS - 1);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    if constexpr (i < Q) {
         const int j = t + i * T;
         const int k = (Ns == 1) ? 0 : (j % Ns);
         cpx<Real> a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r] = v[i + r * Q];
         if constexpr (Ns > 1) {
-            // keep the compiler from hoisting twiddle loads out of loops over
-            // wavelengths (they would stay live in registers across FFTs)
-            asm volatile("" ::: "memory");
-            apply_twiddles<Real, R>(a, tw + twiddle_offset<L, V>(s) + k * R);
+            if constexpr (mode != 0 && RowCfg<Real, L, V>::TWC_ON) {
+                constexpr long long C = (mode == 2) ? (long long)(i % (Ns / T)) * T : 0;
+                apply_twiddles<Real, R, C, (long long)Ns * R>(a, tg);
+            } else {
+                // keep the compiler from hoisting twiddle loads out of loops
+                // over wavelengths (they would stay live in registers)
+                asm volatile("" ::: "memory");
+                cpx<Real> bv[tw_nbase<R>()];
+                load_bases<Real, R>(bv, tw + twiddle_offset<L, V>(s) + k * R);
+                tg.build(bv);
+                apply_twiddles<Real, R, 0, 1>(a, tg);
+            }
         }
         Dft<R, -1, Real>::run(a);
         if constexpr (last) {
@@ -123,21 +252,34 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<R
 #pragma unroll
             for (int r = 0; r < R; ++r) lds[lds_index<L>(base + r * Ns)] = a[r];
         }
+        stage_butterflies<Real, L, V, s, i + 1>(v, lds, t, tw, twc, tg);
     }
-    if constexpr (!last) {
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(t + m * T)];
-        __syncthreads();
-        fft_stage<Real, L, V, s + 1>(v, lds, t, tw);
+}
+
+// Copies each workgroup's base twiddles to the LDS cache (before the first
+// FFT; the caller synchronises).
+template <typename Real, int L, int V, int s = 1>
+__device__ __forceinline__ void fill_tw_cache(cpx<Real> *twc, const cpx<Real> *__restrict__ tw, int tid, int nthr) {
+    if constexpr (s < Plan<L, V>::NS) {
+        constexpr int mode = tw_mode<L, V>(s);
+        if constexpr (mode != 0) {
+            constexpr int R = Plan<L, V>::R[s], nb = tw_nbase<R>(), cnt = tw_cache_count<L, V>(s);
+            cpx<Real> *dst = twc + tw_cache_offset<L, V>(s);
+            const cpx<Real> *src = tw + twiddle_offset<L, V>(s);
+            for (int e = tid; e < cnt * nb; e += nthr) {
+                const int idx = e / nb, b = e - idx * nb;
+                dst[e] = src[idx * R + tw_base_power<R>(b)];
+            }
+        }
+        fill_tw_cache<Real, L, V, s + 1>(twc, tw, tid, nthr);
     }
 }
 
 // Forward DFT of the register row (natural order in, natural order out).
 template <typename Real, int L, int V>
 __device__ __forceinline__ void fft_forward(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<Real> *lds, int t,
-                                            const cpx<Real> *__restrict__ tw) {
-    fft_stage<Real, L, V, 0>(v, lds, t, tw);
+                                            const cpx<Real> *__restrict__ tw, const cpx<Real> *twc) {
+    fft_stage<Real, L, V, 0>(v, lds, t, tw, twc);
 }
 
 // ---------------------------------------------------------------- pointwise
@@ -245,6 +387,7 @@ template <typename Real, int L, int V> struct RowState {
     const RowProgram *prog;
     cpx<Real> *lds;
     const cpx<Real> *tw;
+    const cpx<Real> *twc;  // twiddle cache in LDS (or NULL)
     double *red;
     int t, tid, g, batch, row, it;
     bool valid;
@@ -291,12 +434,12 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)st.keep[m]);
     } else if constexpr (CODE == ROP_FFT_FWD) {
-        fft_forward<Real, L, V>(v, st.lds, st.t, st.tw);
+        fft_forward<Real, L, V>(v, st.lds, st.t, st.tw, st.twc);
     } else if constexpr (CODE == ROP_FFT_INV) {
         // IDFT(v) = conj(DFT(conj(v)))
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
-        fft_forward<Real, L, V>(v, st.lds, st.t, st.tw);
+        fft_forward<Real, L, V>(v, st.lds, st.t, st.tw, st.twc);
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
     } else if constexpr (CODE == ROP_MUL_TAB) {
@@ -435,6 +578,13 @@ __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_
     st.lds = reinterpret_cast<cpx<Real> *>(lds_raw) + bsub * Cfg::LDS_STRIDE;
     st.red = reinterpret_cast<double *>(lds_raw);
     st.tw = tw;
+    st.twc = nullptr;
+    if constexpr (Cfg::TWC_ON) {
+        cpx<Real> *twc = reinterpret_cast<cpx<Real> *>(lds_raw + Cfg::FFT_LDS_BYTES);
+        fill_tw_cache<Real, L, V>(twc, tw, st.tid, Cfg::THREADS);
+        __syncthreads();
+        st.twc = twc;
+    }
     st.it = 0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
