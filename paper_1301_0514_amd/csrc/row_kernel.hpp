@@ -414,8 +414,14 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         }
     } else if constexpr (CODE == ROP_LOAD_R) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
+        if (op.flags & RF_PAIR) {  // two real rows as one complex row
+            const Real *src2 = static_cast<const Real *>(op.ptr2) + off;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = {src[m * T], (Real)0};
+            for (int m = 0; m < E; ++m) v[m] = {src[m * T], src2[m * T]};
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = {src[m * T], (Real)0};
+        }
     } else if constexpr (CODE == ROP_LOAD_PHASE) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
         const double sturn = s * (0.5 / kPi);
@@ -489,6 +495,11 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
             const Real sc = (Real)op.param;
 #pragma unroll
             for (int m = 0; m < E; ++m) dst[m * T] = sc * v[m].re;
+            if (op.flags & RF_PAIR) {  // the imaginary part to the second row
+                Real *dst2 = static_cast<Real *>(op.ptr2) + off;
+#pragma unroll
+                for (int m = 0; m < E; ++m) dst2[m * T] = sc * v[m].im;
+            }
         }
     } else if constexpr (CODE == ROP_ACC_ABS2) {
         const Real w = (Real)((op.flags & RF_ITER_WEIGHT) ? st.prog->weight[st.it] : op.param);

@@ -48,7 +48,8 @@ enum : int32_t {
     RF_CONJ = 1,       // ROP_MUL_TAB: multiply by the conjugate
     RF_ADD = 1,        // ROP_STORE_ACC: accumulate into dst
     RF_ITER_SCALE = 2, // phase scale s = scale[it] (else param)
-    RF_ITER_WEIGHT = 4 // ROP_ACC_ABS2: w = weight[it] (else param)
+    RF_ITER_WEIGHT = 4, // ROP_ACC_ABS2: w = weight[it] (else param)
+    RF_PAIR = 8         // ROP_LOAD_R: v = (src[e], ptr2[e]); ROP_STORE_R: dst[e] = Re, ptr2[e] = Im
 };
 
 // Address of element e of row `row` of batch b at loop iteration it:

@@ -1069,6 +1069,9 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
     const size_t cbytes = 2 * rb1;
     const size_t budget = workspace_budget();
     const int nb_max = (int)std::max<size_t>(1, budget / (cbytes * (2 + 2 * (size_t)n_r)));
+    // The disk kernel is real, so two real patterns a and b ride in one
+    // complex transform: (a + i b) * d = a * d + i (b * d).  Realisations are
+    // paired; an odd last one goes alone (imaginary part zero).
     for (int b0 = 0; b0 < n_real; b0 += nb_max) {
         const int nb = std::min(nb_max, n_real - b0);
         void *ws = nullptr;
@@ -1079,28 +1082,44 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
         char *W2 = base + c.take(cbytes * nb);
         char *V1 = base + c.take(cbytes * nb * n_r);
         char *V2 = base + c.take(cbytes * nb * n_r);
-        const char *Iin = static_cast<const char *>(I_in) + (size_t)b0 * rb1;
-        ProgBuilder a(N, (int64_t)nb * N);
-        a.op(ROP_LOAD_R, Iin, nn(N), N).op(ROP_FFT_FWD).op(ROP_STORE_C, W1, nn(N), N);
-        if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream)) return rc;
-        if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
-        ProgBuilder b(N, (int64_t)nb * N);
-        b.p.n_iter = n_r;
-        b.op(ROP_LOAD_C, W2, nn(N), N)
-            .op(ROP_FFT_FWD)
-            .op(ROP_SAVE)
-            .op(ROP_LOOP)
-            .op(ROP_RESTORE)
-            .op(ROP_MUL_RTAB2D, D, 0, N, nn(N))
-            .op(ROP_FFT_INV)
-            .op(ROP_STORE_C, V1, (int64_t)n_r * nn(N), N, nn(N))
-            .op(ROP_ENDLOOP);
-        if (int rc = run_row<ProgSmearMidTag>(dtype, N, b.p, b.n, stream)) return rc;
-        if (int rc = transpose(V1, V2, N, (int64_t)nb * n_r, (int)(cbytes / nn(N)), stream)) return rc;
-        ProgBuilder d(N, (int64_t)nb * n_r * N);
-        char *Iout = static_cast<char *>(I_out) + (size_t)b0 * n_r * rb1;
-        d.op(ROP_LOAD_C, V2, nn(N), N).op(ROP_FFT_INV).op(ROP_STORE_R, Iout, nn(N), N, 0, 0, 1.0);
-        if (int rc = run_row<ProgInvReTag>(dtype, N, d.p, d.n, stream)) return rc;
+        for (int pb = 0; pb < nb;) {
+            const bool pair = nb - pb >= 2;
+            const int np = pair ? (nb - pb) / 2 : 1;  // complex transforms in this group
+            const int step = pair ? 2 : 1;            // realisations per transform
+            const char *Iin = static_cast<const char *>(I_in) + (size_t)(b0 + pb) * rb1;
+            ProgBuilder a(N, (int64_t)np * N);
+            a.op(ROP_LOAD_R, Iin, (int64_t)step * nn(N), N, 0, pair ? RF_PAIR : 0, 0.0,
+                 pair ? const_cast<char *>(Iin) + rb1 : nullptr)
+                .op(ROP_FFT_FWD)
+                .op(ROP_STORE_C, W1, nn(N), N);
+            if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream)) return rc;
+            if (int rc = transpose(W1, W2, N, np, (int)(cbytes / nn(N)), stream)) return rc;
+            ProgBuilder b(N, (int64_t)np * N);
+            b.p.n_iter = n_r;
+            b.op(ROP_LOAD_C, W2, nn(N), N)
+                .op(ROP_FFT_FWD)
+                .op(ROP_SAVE)
+                .op(ROP_LOOP)
+                .op(ROP_RESTORE)
+                .op(ROP_MUL_RTAB2D, D, 0, N, nn(N))
+                .op(ROP_FFT_INV)
+                .op(ROP_STORE_C, V1, (int64_t)n_r * nn(N), N, nn(N))
+                .op(ROP_ENDLOOP);
+            if (int rc = run_row<ProgSmearMidTag>(dtype, N, b.p, b.n, stream)) return rc;
+            if (int rc = transpose(V1, V2, N, (int64_t)np * n_r, (int)(cbytes / nn(N)), stream)) return rc;
+            // I_out[b][r]: transform q holds realisations b0 + pb + step q (and + 1)
+            char *Iout = static_cast<char *>(I_out) + (size_t)(b0 + pb) * n_r * rb1;
+            for (int r = 0; r < n_r; ++r) {
+                ProgBuilder d(N, (int64_t)np * N);
+                char *dst = Iout + (size_t)r * rb1;
+                d.op(ROP_LOAD_C, V2 + (size_t)r * cbytes, (int64_t)n_r * nn(N), N)
+                    .op(ROP_FFT_INV)
+                    .op(ROP_STORE_R, dst, (int64_t)step * n_r * nn(N), N, 0, pair ? RF_PAIR : 0, 1.0,
+                        pair ? dst + (size_t)n_r * rb1 : nullptr);
+                if (int rc = run_row<ProgInvReTag>(dtype, N, d.p, d.n, stream)) return rc;
+            }
+            pb += np * step;
+        }
     }
     return PS_OK;
 }

@@ -192,6 +192,25 @@ def test_smear(S, oracle, dtype, N):
             assert np.abs(out[b, j] - ref).max() < tol * np.abs(I[b]).max()
 
 
+@pytest.mark.parametrize("n", [3, 5])
+def test_smear_pairs_and_odd_batch(S, oracle, n):
+    # realisations share complex transforms two by two; the odd last one
+    # goes alone -- every output against the oracle, several radii
+    N = 100
+    radii = [0.0, 3.0, 11.0]
+    I = inputs.intensity_field(N, seed=40 + n, n=n)
+    out = host(S.source_smear(dev(I, torch.float64), 1.0, radii))
+    assert out.shape == (n, len(radii), N, N)
+    for b in range(n):
+        for j, Rs in enumerate(radii):
+            assert np.abs(out[b, j] - oracle.smear(I[b], Rs)).max() < 1e-11 * np.abs(I[b]).max()
+    # in place with one radius
+    t = dev(I, torch.float64)
+    S.source_smear(t, 1.0, [3.0], out=t.view(n, 1, N, N))
+    for b in range(n):
+        assert np.abs(host(t)[b] - oracle.smear(I[b], 3.0)).max() < 1e-11 * np.abs(I[b]).max()
+
+
 def test_smear_in_place_and_units(S, oracle):
     N = 64
     I = inputs.intensity_field(N, seed=3)
@@ -226,12 +245,14 @@ def test_autograd_matches_vjp(S, oracle):
     N, rho = 64, 5.0
     lam = 5e-7
     z = 2 * np.pi * rho ** 2 / lam
-    phi = dev(inputs.smooth_phase_field(N, seed=8, sigma=3.0, n=1), torch.float64).requires_grad_(True)
-    It = dev(inputs.intensity_field(N, seed=9), torch.float64)
+    phi_np = inputs.smooth_phase_field(N, seed=8, sigma=3.0, n=1)
+    It_np = inputs.intensity_field(N, seed=9)
+    phi = dev(phi_np, torch.float64).requires_grad_(True)
+    It = dev(It_np, torch.float64)
     I = S.fresnel_intensity(phi, 1.0, lam, z)
     loss = ((I - It) ** 2).sum()
     loss.backward()
-    ref = oracle.propagate_vjp(host(phi)[0], rho, 1.0, 2 * (oracle.propagate(host(phi)[0], rho) - host(It)[0]))
+    ref = oracle.propagate_vjp(phi_np[0], rho, 1.0, 2 * (oracle.propagate(phi_np[0], rho) - It_np[0]))
     assert np.abs(host(phi.grad)[0] - ref).max() < 1e-9 * np.abs(ref).max()
 
 
