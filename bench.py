@@ -31,16 +31,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# device sources of the row-pass kernels (the FFT passes that dominate the step)
+# device sources of the row-pass kernels (the FFT passes) and of the
+# transposes, the two kernel families that dominate the step
 ROW_KERNEL_SOURCES = ("device_common.hpp", "fft_plan.hpp", "row_program.h", "row_kernel.hpp", "row_launch.h",
                       "row_inst.hip", "twiddles.cpp")
+AUX_KERNEL_SOURCES = ("device_common.hpp", "aux_kernels.h", "aux_kernels.hip")
 
 
-def source_hash() -> str:
-    """Hash of the row-pass kernel sources; ties a stored counter profile to
-    the kernel it was taken on."""
+def kernel_sources(kernel: str):
+    return AUX_KERNEL_SOURCES if kernel.startswith("transpose_") else ROW_KERNEL_SOURCES
+
+
+def source_hash(kernel: str = "row_") -> str:
+    """Hash of the device sources of `kernel` (row passes or transposes);
+    ties a stored counter profile to the kernel it was taken on."""
     h = hashlib.sha256()
-    for name in ROW_KERNEL_SOURCES:
+    for name in kernel_sources(kernel):
         with open(os.path.join(ROOT, "paper_1301_0514_amd", "csrc", name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
@@ -50,8 +56,10 @@ def source_hash() -> str:
 def stored_traffic(kernel: str, plan_variant: int | None = None):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
     summary (profiles/traffic_*.txt), if it was taken on the current kernel
-    sources and FFT plan variant."""
-    want = source_hash()
+    sources and, for row passes, FFT plan variant."""
+    want = source_hash(kernel)
+    if not kernel.startswith("row_"):
+        plan_variant = None
     for p in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt")):
         vals = {}
         with open(p) as fh:
