@@ -34,8 +34,9 @@ def log(*a):
 # device sources of the row-pass kernels (the FFT passes) and of the
 # transposes, the two kernel families that dominate the step
 ROW_KERNEL_SOURCES = ("device_common.hpp", "fft_plan.hpp", "row_program.h", "row_kernel.hpp", "row_launch.h",
+                      "transpose_tile.hpp",
                       "row_inst.hip", "twiddles.cpp")
-AUX_KERNEL_SOURCES = ("device_common.hpp", "aux_kernels.h", "aux_kernels.hip")
+AUX_KERNEL_SOURCES = ("device_common.hpp", "aux_kernels.h", "aux_kernels.hip", "transpose_tile.hpp")
 
 
 def kernel_sources(kernel: str):
@@ -199,7 +200,9 @@ def main(argv=None) -> int:
     for k, v in kernels.items():
         log("  %-40s %8.3f ms/step  %6.1f launches  %7.1f GB/s  %6.2f TFLOP/s" % (
             k, v["ms_per_step"], v["launches_per_step"], v["algorithmic_GBps"], v["algorithmic_TFLOPs"]))
-    if flops_per_launch > 0:
+    # the bound is the resource the kernel uses the larger fraction of (row
+    # passes that carry transposes move more bytes than their FFTs can hide)
+    if flops_per_launch > 0 and tflops / FP32_VECTOR_PEAK_TFLOPS >= gbps / HBM_PEAK_GBS:
         roofline = {"bound": "alu", "kernel": dname, "achieved": tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                     "algorithmic_flops_per_launch": flops_per_launch,
@@ -209,6 +212,9 @@ def main(argv=None) -> int:
         roofline = {"bound": "hbm", "kernel": dname, "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbps / HBM_PEAK_GBS, "traffic": traffic,
                     "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms}
+        if flops_per_launch > 0:
+            roofline.update({"algorithmic_flops_per_launch": flops_per_launch, "alu_achieved_TFLOPs": tflops,
+                             "alu_frac": tflops / FP32_VECTOR_PEAK_TFLOPS})
     # whole-step algorithmic bytes: the sum over kernels of their operands
     step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
 

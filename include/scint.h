@@ -136,6 +136,13 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
  *                      (equal weights); weights >= 0 with a positive sum
  *   n_lambda           1 .. 4096
  *   phi_ref   device [n_real][N][N] real;  I_out device [n_real][N][N] real
+ * Work is split into jobs of up to 64 wavelengths and as many realisations as
+ * the workspace budget allows (ps_set_workspace_budget).  In FP32 from
+ * N = 2048 up, with two or more jobs, the jobs are pipelined: the transpose
+ * between the two 1-D passes of one job runs inside the launches of the
+ * neighbouring jobs' passes, which takes twice the workspace of the plain
+ * loop and gives the same result bit for bit for the same job split
+ * (environment SCINT_PIPELINE=0 turns it off).
  */
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref,
                                double lambda_ref, const double *lambdas,
@@ -320,6 +327,17 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
 int ps_num_plan_variants(int N, int dtype);
 int ps_plan_variant(int N, int dtype, int *variant_out, float *ms_out);
 int ps_set_plan_variant(int N, int dtype, int variant);
+
+/*
+ * ps_set_workspace_budget -- upper bound, in bytes, on the workspace that
+ * later calls on the current device plan for; whole-batch work is split into
+ * chunks that fit it (the chunking can change FP32 rounding of sums over
+ * wavelength chunks).  0 restores the default: half the free device memory
+ * at the next call, at most 96 GiB.  Values below 64 MiB are rejected
+ * (PS_E_PARAM).  A single grid that needs more than the budget still gets
+ * the memory it needs.
+ */
+int ps_set_workspace_budget(size_t bytes);
 
 /*
  * Kernel timing (instrumentation).  While enabled, every kernel the library

@@ -26,6 +26,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 PROGRAMS = ["ProgNoise", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgPropIntensity",
             "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX",
             "ProgApertureX", "ProgAbs2"]
+# programs built for float only (their side transposes are complex64)
+PROGRAMS_F32 = ["ProgPhasePropT", "ProgPropIntensityT"]
 
 # gfx950 only; packed FP32 instructions are disabled (the compiler would
 # otherwise form them from float code).
@@ -37,7 +39,7 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 def _jobs() -> list[tuple[list[str], str]]:
     jobs = []
     for real, is64 in (("float", 0), ("double", 1)):
-        for prog in PROGRAMS:
+        for prog in PROGRAMS + (PROGRAMS_F32 if not is64 else []):
             obj = os.path.join(BUILD, f"row_{real}_{prog}.o")
             cmd = [HIPCC, *DEVICE_FLAGS, f"-DSCINT_REAL={real}", f"-DSCINT_PROG={prog}",
                    f"-DSCINT_IS_F64={is64}", "-c", os.path.join(CSRC, "row_inst.hip"), "-o", obj]

@@ -5,72 +5,18 @@
 
 #include "aux_kernels.h"
 #include "device_common.hpp"
+#include "transpose_tile.hpp"
 
 namespace scint {
 
 // ---------------------------------------------------------------- transpose
-// Two horizontally adjacent 64 x 64 tiles per workgroup (64 rows x 128
-// columns) through LDS, 256 threads.  The tiles are held as element pairs
-// (16 bytes for complex64, 8 for float): a lane loads one pair of a source
-// row, so each source row is read as one contiguous 1 KB (512 B) run.  On
-// the way out a lane takes the pair of columns (2q, 2q+1) from the two source
-// rows (2l, 2l+1), transposes that 2 x 2 block in registers and writes one
-// pair to each of the output rows 2q and 2q+1, as contiguous runs.  Pair q of
-// tile row y is kept in LDS slot q ^ ((y >> 1) & 31): the 32 lanes that read
-// one pair column then touch 32 distinct slots, and each row's write is a
-// permutation within the row, so neither phase has bank conflicts.  N is
-// even (every supported size is), so a pair never straddles the edge of a
-// ragged tile.
-template <typename T> struct alignas(2 * sizeof(T)) Pair {
-    T a, b;
-};
-constexpr int kTransposeTilesX = 2;
-
+// One 64 x 128 unit per workgroup of 256 threads (transpose_tile.hpp): grid
+// x over units along the columns, y along the rows, z over the batch.
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_pair_kernel(const T *__restrict__ in, T *__restrict__ out, int N) {
-    __shared__ Pair<T> tile[kTransposeTilesX][64][32];
-    const int lx = threadIdx.x % 32, ly = threadIdx.x / 32;  // 32 pair-lanes x 8 rows
-    const int y0 = blockIdx.y * 64;
+    __shared__ TransposeTile<T> tile;
     const int64_t base = (int64_t)blockIdx.z * N * N;
-    const T *src = in + base;
-    T *dst = out + base;
-    // Unguarded loads at addresses clamped into the matrix, so that all of
-    // them are in flight at once (a guarded load is waited for on its own).
-    // The slots they fill for positions outside the matrix are never read.
-    Pair<T> v[kTransposeTilesX][8];
-#pragma unroll
-    for (int tt = 0; tt < kTransposeTilesX; ++tt) {
-        const int xc = min((int)(blockIdx.x * kTransposeTilesX + tt) * 64 + 2 * lx, N - 2);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int yc = min(y0 + ly + 8 * i, N - 1);
-            v[tt][i] = *reinterpret_cast<const Pair<T> *>(src + (int64_t)yc * N + xc);
-        }
-    }
-#pragma unroll
-    for (int tt = 0; tt < kTransposeTilesX; ++tt) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int r = ly + 8 * i;
-            tile[tt][r][lx ^ ((r >> 1) & 31)] = v[tt][i];
-        }
-    }
-    __syncthreads();
-    const int ya = y0 + 2 * lx;
-#pragma unroll
-    for (int tt = 0; tt < kTransposeTilesX; ++tt) {
-        const int x0 = (blockIdx.x * kTransposeTilesX + tt) * 64;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q = ly + 8 * i, x = x0 + 2 * q;  // output rows x, x + 1
-            if (x < N && ya < N) {
-                const Pair<T> u = tile[tt][2 * lx][q ^ lx];      // source row ya: columns x, x + 1
-                const Pair<T> w = tile[tt][2 * lx + 1][q ^ lx];  // source row ya + 1
-                *reinterpret_cast<Pair<T> *>(dst + (int64_t)x * N + ya) = Pair<T>{u.a, w.a};
-                *reinterpret_cast<Pair<T> *>(dst + (int64_t)(x + 1) * N + ya) = Pair<T>{u.b, w.b};
-            }
-        }
-    }
+    transpose_unit<T, 256>(in + base, out + base, N, blockIdx.x, blockIdx.y, tile, threadIdx.x);
 }
 
 // complex128: one 16-byte element per lane, TILE x TILE tile.
@@ -112,7 +58,7 @@ hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, in
     for (int64_t b0 = 0; b0 < nbatch; b0 += 65535) {
         const int nb = (int)((nbatch - b0) < 65535 ? (nbatch - b0) : 65535);
         const int64_t off = b0 * (int64_t)N * N;
-        const dim3 grid64((N + 64 * kTransposeTilesX - 1) / (64 * kTransposeTilesX), (N + 63) / 64, nb);
+        const dim3 grid64(transpose_units_x(N), transpose_units_y(N), nb);
         if (elem_bytes == 4) {
             hipLaunchKernelGGL((transpose_pair_kernel<float>), grid64, dim3(256), 0, stream,
                                static_cast<const float *>(in) + off, static_cast<float *>(out) + off, N);

@@ -19,9 +19,28 @@ namespace scint {
 template <int L, int V>
 static hipError_t launch_one(const RowProgram &prog, const void *tw, hipStream_t stream) {
     using Cfg = RowCfg<SCINT_REAL, L, V>;
-    const int grid = (prog.total_rows + Cfg::B - 1) / Cfg::B;
-    hipLaunchKernelGGL((row_kernel<SCINT_REAL, L, V, SCINT_PROG>), dim3(grid), dim3(Cfg::THREADS), 0, stream,
-                       prog, static_cast<const cpx<SCINT_REAL> *>(tw));
+    const int rows_blocks = (prog.total_rows + Cfg::B - 1) / Cfg::B;
+    if constexpr (has_side<SCINT_PROG>()) {
+        // groups of fft_blocks row workgroups and side_blocks transpose
+        // workgroups; the units are spread evenly over the latter
+        RowProgram p = prog;
+        RowSide &sd = p.side;
+        const int64_t units = sd.u1 - sd.u0;
+        if (sd.fft_blocks < 1 || sd.side_blocks < 1 || units < 1 || sd.u0 < 0 || !sd.in || !sd.out)
+            return hipErrorInvalidValue;
+        sd.groups = (rows_blocks + sd.fft_blocks - 1) / sd.fft_blocks;
+        const int64_t nside = (int64_t)sd.groups * sd.side_blocks;
+        const int64_t per = (units + nside - 1) / nside;
+        if (per > (1 << 30) || (int64_t)sd.groups * (sd.fft_blocks + sd.side_blocks) > (1ll << 31) - 1)
+            return hipErrorInvalidValue;
+        sd.units_per_block = (int32_t)per;
+        const int grid = sd.groups * (sd.fft_blocks + sd.side_blocks);
+        hipLaunchKernelGGL((row_kernel<SCINT_REAL, L, V, SCINT_PROG>), dim3(grid), dim3(Cfg::THREADS), 0, stream, p,
+                           static_cast<const cpx<SCINT_REAL> *>(tw));
+    } else {
+        hipLaunchKernelGGL((row_kernel<SCINT_REAL, L, V, SCINT_PROG>), dim3(rows_blocks), dim3(Cfg::THREADS), 0,
+                           stream, prog, static_cast<const cpx<SCINT_REAL> *>(tw));
+    }
     return hipGetLastError();
 }
 

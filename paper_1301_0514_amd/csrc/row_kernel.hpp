@@ -6,6 +6,9 @@
 #include "device_common.hpp"
 #include "fft_plan.hpp"
 #include "row_program.h"
+#include "transpose_tile.hpp"
+
+#include <type_traits>
 
 namespace scint {
 
@@ -548,6 +551,8 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         }
         if (st.t == 0 && valid) static_cast<double *>(op.ptr2)[st.g] = red[st.tid];
         __syncthreads();
+    } else if constexpr (CODE == ROP_SIDE_T) {
+        // the side transposes run in workgroups of their own (row_kernel)
     } else {
         static_assert(CODE == ROP_END, "unknown row op");
     }
@@ -570,19 +575,67 @@ __device__ __forceinline__ void run_ops(RowState<Real, L, V> &st) {
     }
 }
 
+template <class Ops> constexpr bool has_side() { return Ops::n > 0 && Ops::code[0] == ROP_SIDE_T; }
+
+// LDS of a row kernel: the row pass's, or the transpose tile's if larger
+// (programs with side transposes)
+template <typename Real, int L, int V, class Ops> constexpr int row_kernel_lds() {
+    constexpr int a = RowCfg<Real, L, V>::LDS_BYTES, b = (int)sizeof(TransposeTile<cpx<float>>);
+    return has_side<Ops>() && a < b ? b : a;
+}
+
+// The side transposes of one transpose workgroup (number sb of the launch):
+// its units_per_block consecutive units of [u0, u1), one after the other.
+// Their data is touched once, so it is streamed with nontemporal accesses
+// and leaves the cached tables and phase rows of the row workgroups alone.
+template <int NT>
+__device__ __forceinline__ void side_transposes(const RowSide &sd, int N, int sb, unsigned char *lds, int tid) {
+    const int nx = transpose_units_x(N), ny = transpose_units_y(N);
+    const int64_t per = (int64_t)nx * ny, nn = (int64_t)N * N;
+    int64_t u = sd.u0 + (int64_t)sb * sd.units_per_block;
+    const int64_t end = min(u + (int64_t)sd.units_per_block, sd.u1);
+    auto &tile = *reinterpret_cast<TransposeTile<cpx<float>> *>(lds);
+    const cpx<float> *in = static_cast<const cpx<float> *>(sd.in);
+    cpx<float> *out = static_cast<cpx<float> *>(sd.out);
+    for (; u < end; ++u) {
+        const int64_t z = u / per;
+        const int rem = (int)(u - z * per);
+        const int uy = rem / nx, ux = rem - uy * nx;
+        transpose_unit<cpx<float>, NT, true>(in + z * nn, out + z * nn, N, ux, uy, tile, tid);
+        __syncthreads();  // the tile is reused by the next unit
+    }
+}
+
 template <typename Real, int L, int V, class Ops>
 __global__ __launch_bounds__((RowCfg<Real, L, V>::THREADS))
 __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_kernel(const RowProgram prog,
                                                                            const cpx<Real> *__restrict__ tw) {
     using Cfg = RowCfg<Real, L, V>;
     constexpr int E = Plan<L, V>::E, T = Plan<L, V>::T, B = Cfg::B;
-    __shared__ __align__(16) unsigned char lds_raw[Cfg::LDS_BYTES];
+    __shared__ __align__(16) unsigned char lds_raw[row_kernel_lds<Real, L, V, Ops>()];
+    int rb = blockIdx.x;  // row workgroup number
+    if constexpr (has_side<Ops>()) {
+        // groups of fft_blocks row workgroups followed by side_blocks
+        // transpose workgroups (uniform per workgroup, so the early returns
+        // come before any barrier)
+        static_assert(std::is_same<Real, float>::value, "side transposes are complex64 only");
+        const RowSide &sd = prog.side;
+        const int G = sd.fft_blocks + sd.side_blocks;
+        const int grp = blockIdx.x / G, r = blockIdx.x - grp * G;
+        if (r >= sd.fft_blocks) {
+            side_transposes<Cfg::THREADS>(sd, prog.N, grp * sd.side_blocks + (r - sd.fft_blocks), lds_raw,
+                                          threadIdx.x);
+            return;
+        }
+        rb = grp * sd.fft_blocks + r;
+        if ((int64_t)rb * B >= prog.total_rows) return;
+    }
     RowState<Real, L, V> st;
     st.prog = &prog;
     st.tid = threadIdx.x;
     const int bsub = st.tid / T;
     st.t = st.tid - bsub * T;
-    st.g = blockIdx.x * B + bsub;  // global row over the batch
+    st.g = rb * B + bsub;  // global row over the batch
     st.valid = st.g < prog.total_rows;
     st.batch = st.valid ? st.g / L : 0;
     st.row = st.valid ? st.g - st.batch * L : 0;
@@ -617,6 +670,11 @@ using ProgPhaseProp = OpList<ROP_LOOP, ROP_LOAD_PHASE, ROP_FFT_FWD, ROP_MUL_TAB,
                              ROP_ENDLOOP>;
 using ProgPropIntensity = OpList<ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_ACC_ABS2,
                                  ROP_ENDLOOP, ROP_STORE_ACC>;
+// the two propagation passes carrying transposes of other data (RowSide)
+using ProgPhasePropT = OpList<ROP_SIDE_T, ROP_LOOP, ROP_LOAD_PHASE, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV,
+                              ROP_STORE_C, ROP_ENDLOOP>;
+using ProgPropIntensityT = OpList<ROP_SIDE_T, ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV,
+                                  ROP_ACC_ABS2, ROP_ENDLOOP, ROP_STORE_ACC>;
 using ProgRealFwd = OpList<ROP_LOAD_R, ROP_FFT_FWD, ROP_STORE_C>;
 using ProgFwdRe = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_STORE_R>;
 using ProgSmearMid = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_SAVE, ROP_LOOP, ROP_RESTORE, ROP_MUL_RTAB2D,

@@ -21,10 +21,14 @@ struct ProgVjpYTag;
 struct ProgVjpXTag;
 struct ProgApertureXTag;
 struct ProgAbs2Tag;
+struct ProgPhasePropTTag;     // complex64 only
+struct ProgPropIntensityTTag;  // complex64 only
 
 // Launches program Tag on total_rows rows of length L (the grid size N) with
 // plan variant V; tw is the device twiddle table of that plan in the same
-// precision.  Returns hipErrorInvalidValue for an unsupported (L, V).
+// precision.  Returns hipErrorInvalidValue for an unsupported (L, V).  For
+// programs with side transposes the launcher sizes the grid from
+// prog.side.fft_blocks and side_blocks and fills groups and units_per_block.
 template <typename Real, class Tag>
 hipError_t launch_row(int L, int V, const RowProgram &prog, const void *tw, hipStream_t stream);
 

@@ -41,6 +41,7 @@ enum RowOpCode : int32_t {
     ROP_LOOP,        // start of the repeated range
     ROP_ENDLOOP,     // end of the repeated range
     ROP_MUL_ROWTAB,  // v *= tab[row]  (complex, one factor per row)
+    ROP_SIDE_T,      // first op only: the launch also runs the transposes of RowProgram::side
 };
 
 // Flag bits
@@ -69,8 +70,26 @@ struct RowOp {
 constexpr int kRowMaxOps = 20;
 constexpr int kRowMaxIter = 64;
 
+// Transposes a row pass carries as extra workgroups of its own launch
+// (programs whose first op is ROP_SIDE_T; complex64 only): units [u0, u1) of
+// the N x N matrices at `in`, written transposed to the same place in `out`.
+// Unit u is matrix u / (ux uy), then row band, then column band, with
+// ux x uy units of 64 rows by 128 columns per matrix (transpose_tile.hpp).
+// The grid is made of `groups` groups, each of fft_blocks row workgroups
+// followed by side_blocks transpose workgroups that take units_per_block
+// consecutive units each; the launcher fills groups and units_per_block.
+// The row pass and the transposes must not touch each other's data.
+struct RowSide {
+    const void *in;
+    void *out;
+    int64_t u0, u1;
+    int32_t fft_blocks, side_blocks;
+    int32_t groups, units_per_block;
+};
+
 struct RowProgram {
     RowOp op[kRowMaxOps];
+    RowSide side;
     int32_t n_iter;      // iterations of the loop range (>= 1)
     int32_t N;           // row length (= grid size)
     int32_t total_rows;  // batch * N

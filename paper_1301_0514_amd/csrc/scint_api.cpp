@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -26,6 +27,7 @@
 #include "aux_kernels.h"
 #include "fft_plan.hpp"
 #include "row_launch.h"
+#include "transpose_tile.hpp"
 
 using namespace scint;
 
@@ -369,6 +371,8 @@ SCINT_PROG_NAME(ProgVjpY)
 SCINT_PROG_NAME(ProgVjpX)
 SCINT_PROG_NAME(ProgApertureX)
 SCINT_PROG_NAME(ProgAbs2)
+SCINT_PROG_NAME(ProgPhasePropT)
+SCINT_PROG_NAME(ProgPropIntensityT)
 #undef SCINT_PROG_NAME
 
 int plan_variant(int N, int dtype, int *V);
@@ -387,6 +391,43 @@ template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_op
         timing_end(stream, t0,
                    std::string("row_") + prog_name<Tag>() + "_" + real_name(dtype) + "_N" + std::to_string(N),
                    row_bytes(p, n_ops, dtype), row_flops(p, n_ops));
+    return PS_OK;
+}
+
+// Elements of the N x N matrices that side-transpose units [u0, u1) cover
+// (units of 64 rows by 128 columns, ragged at the right and bottom edges).
+double side_elements(const RowSide &sd, int N) {
+    const int nx = transpose_units_x(N), ny = transpose_units_y(N);
+    const int64_t per = (int64_t)nx * ny;
+    auto unit_elems = [&](int64_t u) {
+        const int rem = (int)(u % per), uy = rem / nx, ux = rem - uy * nx;
+        return (double)std::min(kTransposeUnitRows, N - uy * kTransposeUnitRows) *
+               (double)std::min(kTransposeUnitCols, N - ux * kTransposeUnitCols);
+    };
+    double e = 0.0;
+    int64_t u = sd.u0;
+    for (; u < sd.u1 && u % per; ++u) e += unit_elems(u);          // head of a partial matrix
+    const int64_t whole = (sd.u1 - u) / per;                        // whole matrices
+    e += (double)whole * N * N;
+    for (u += whole * per; u < sd.u1; ++u) e += unit_elems(u);      // tail
+    return e;
+}
+
+// Row pass whose launch also runs the transposes of p.side (FP32 programs
+// only).  Its timing entry counts their bytes too (each element read once
+// and written once).
+template <class Tag> int run_row_side(int N, const RowProgram &p, int n_ops, hipStream_t stream) {
+    int V = 0;
+    if (int rc = plan_variant(N, PS_F32, &V)) return rc;
+    const void *tw = nullptr;
+    if (int rc = get_twiddles(N, V, PS_F32, &tw)) return rc;
+    hipEvent_t t0 = nullptr;
+    const bool timed = timing_begin(stream, &t0);
+    hipError_t e = launch_row<float, Tag>(N, V, p, tw, stream);
+    if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("row pass launch: ") + hipGetErrorString(e));
+    if (timed)
+        timing_end(stream, t0, std::string("row_") + prog_name<Tag>() + "_f32_N" + std::to_string(N),
+                   row_bytes(p, n_ops, PS_F32) + 16.0 * side_elements(p.side, N), row_flops(p, n_ops));
     return PS_OK;
 }
 
@@ -529,8 +570,9 @@ int64_t nn(int N) { return (int64_t)N * N; }
 
 // Upper bound on workspace bytes a call plans for (whole-batch processing is
 // split into chunks above it): half the free device memory at the first call
-// on the device, at most 48 GiB.  Fixed afterwards, so that a given call
-// always takes the same chunking (and no call queries the device again).
+// on the device, at most 96 GiB, unless ps_set_workspace_budget set it.
+// Fixed afterwards, so that a given call always takes the same chunking (and
+// no call queries the device again).
 size_t workspace_budget() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return (size_t)8 << 30;
@@ -539,7 +581,7 @@ size_t workspace_budget() {
     if (dc.budget == 0) {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = (size_t)16 << 30;
-        dc.budget = std::max<size_t>((size_t)1 << 30, std::min<size_t>((size_t)48 << 30, free_b / 2));
+        dc.budget = std::max<size_t>((size_t)1 << 30, std::min<size_t>((size_t)96 << 30, free_b / 2));
     }
     return dc.budget;
 }
@@ -602,6 +644,16 @@ int ps_set_plan_variant(int N, int dtype, int variant) {
         dc.variant.erase(std::make_pair(N, dtype));
     else
         dc.variant[std::make_pair(N, dtype)] = variant;
+    return PS_OK;
+}
+
+int ps_set_workspace_budget(size_t bytes) {
+    g_last_error.clear();
+    if (bytes != 0 && bytes < ((size_t)64 << 20)) return fail(PS_E_PARAM, "workspace budget below 64 MiB");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    g_cache[dev].budget = bytes;  // 0: the default, taken again at the next call
     return PS_OK;
 }
 
@@ -914,6 +966,144 @@ int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_
     return PS_OK;
 }
 
+// Interleaving of the pipelined propagation below: the share of each job's
+// transpose units carried by the next job's x pass (the rest rides on the y
+// pass two jobs back), and per pass the row workgroups and transpose
+// workgroups of one group of the grid.  Measured at 8192^2 x 32 wavelengths
+// on the MI355X (step times within 1 %: shares of 0.5 to 1 on the x pass;
+// groups of 16 + 4, 32 + 8 or 64 + 16 row + transpose workgroups, i.e. 128
+// units per transpose workgroup; 12-16 % slower: 1 : 1 and 3 : 1 groups):
+// the x pass takes all of a job's transposes (the y pass only the last
+// job's), in groups of 32 + 8.  SCINT_PIPELINE=0 in the environment turns
+// the pipeline off; SCINT_SIDE_SPLIT=<f> and SCINT_SIDE_GROUPS=
+// <rows_x>:<side_x>:<rows_y>:<side_y> override the defaults.
+struct SideCfg {
+    bool on = true;
+    double split = 1.0;
+    int fft_x = 32, side_x = 8, fft_y = 32, side_y = 8;
+};
+static SideCfg side_cfg() {
+    SideCfg c;
+    if (const char *e = std::getenv("SCINT_PIPELINE")) c.on = std::atoi(e) != 0;
+    if (const char *e = std::getenv("SCINT_SIDE_SPLIT")) {
+        const double v = std::atof(e);
+        if (v >= 0.0 && v <= 1.0) c.split = v;
+    }
+    if (const char *e = std::getenv("SCINT_SIDE_GROUPS")) {
+        int a = 0, b = 0, d = 0, f = 0;
+        if (std::sscanf(e, "%d:%d:%d:%d", &a, &b, &d, &f) == 4 && a >= 1 && b >= 1 && d >= 1 && f >= 1 &&
+            a <= 1024 && b <= 1024 && d <= 1024 && f <= 1024) {
+            c.fft_x = a;
+            c.side_x = b;
+            c.fft_y = d;
+            c.side_y = f;
+        }
+    }
+    return c;
+}
+
+// One job of the polychromatic propagation: nb realisations from b0, m
+// wavelengths from j0.
+struct PolyJob {
+    int b0, nb, j0, m;
+};
+
+// Pipelined polychromatic propagation (FP32).  Each job runs the x pass
+// (exp(i s phi), DFT, chirp, IDFT per wavelength) into a raw field buffer,
+// the transpose of that buffer, and the y pass (DFT, chirp, IDFT, weighted
+// |.|^2 summed into Iacc).  Step k launches the x pass of job k, then the y
+// pass of job k-2; the transpose of job k-1 rides on these two launches as
+// extra workgroups (split by SideCfg), so its memory traffic overlaps their
+// FFT arithmetic.  Two raw and two transposed buffers alternate between
+// jobs and three chirp tables between the jobs in flight; the kernels and
+// the order of every sum are those of the plain chunk loop, so the results
+// are the same bit for bit for the same chunking.
+static int poly_pipelined(int N, const char *phi_ref, const std::vector<PolyJob> &jobs, int C, int nb_max,
+                          int n_lambda, const std::vector<double> &rho, const std::vector<double> &scale,
+                          const std::vector<double> &weight, void *I_out, const SideCfg &sc, hipStream_t stream) {
+    const size_t cbytes = (size_t)nn(N) * 8, rb1 = (size_t)nn(N) * 4;
+    const size_t wbytes = cbytes * (size_t)C * nb_max, tbytes = (size_t)C * N * 8;
+    void *ws = nullptr;
+    if (int rc = get_workspace(stream, 4 * wbytes + rb1 * nb_max + 3 * tbytes + 4096, &ws)) return rc;
+    Carver c;
+    char *base = static_cast<char *>(ws);
+    void *W1[2], *W2[2], *H[3];
+    for (auto &w : W1) w = base + c.take(wbytes);
+    for (auto &w : W2) w = base + c.take(wbytes);
+    void *Iacc = base + c.take(rb1 * nb_max);
+    for (auto &h : H) h = base + c.take(tbytes);
+    const int K = (int)jobs.size();
+    const int64_t upm = (int64_t)transpose_units_x(N) * transpose_units_y(N);
+    for (int k = 0; k <= K + 1; ++k) {
+        const bool has_x = k < K, has_y = k >= 2 && k - 2 < K;
+        const int t = k - 1;
+        const bool has_t = t >= 0 && t < K;
+        const int64_t U = has_t ? upm * jobs[t].nb * jobs[t].m : 0;
+        int64_t ua = 0;  // units [0, ua) ride on the x pass, [ua, U) on the y pass
+        if (has_t) ua = (has_x && has_y) ? std::llround((double)U * sc.split) : has_x ? U : 0;
+        auto side = [&](RowSide &sd, int64_t u0, int64_t u1, int fb, int sb) {
+            sd.in = W1[t % 2];
+            sd.out = W2[t % 2];
+            sd.u0 = u0;
+            sd.u1 = u1;
+            sd.fft_blocks = fb;
+            sd.side_blocks = sb;
+        };
+        if (has_x) {
+            const PolyJob &jb = jobs[k];
+            std::vector<double> r(rho.begin() + jb.j0, rho.begin() + jb.j0 + jb.m);
+            if (int rc = chirp_tables(H[k % 3], N, r, PS_F32, true, stream)) return rc;
+            const bool with_side = has_t && ua > 0;
+            ProgBuilder a(N, (int64_t)jb.nb * N);
+            a.p.n_iter = jb.m;
+            for (int j = 0; j < jb.m; ++j) a.p.scale[j] = scale[jb.j0 + j];
+            if (with_side) {
+                a.op(ROP_SIDE_T);
+                side(a.p.side, 0, ua, sc.fft_x, sc.side_x);
+            }
+            a.op(ROP_LOOP)
+                .op(ROP_LOAD_PHASE, phi_ref + (size_t)jb.b0 * rb1, nn(N), N, 0, RF_ITER_SCALE)
+                .op(ROP_FFT_FWD)
+                .op(ROP_MUL_TAB, H[k % 3], 0, 0, N)
+                .op(ROP_FFT_INV)
+                .op(ROP_STORE_C, W1[k % 2], nn(N), N, (int64_t)jb.nb * nn(N))
+                .op(ROP_ENDLOOP);
+            const int rc = with_side ? run_row_side<ProgPhasePropTTag>(N, a.p, a.n, stream)
+                                     : run_row<ProgPhasePropTag>(PS_F32, N, a.p, a.n, stream);
+            if (rc) return rc;
+        }
+        if (has_y) {
+            const PolyJob &jb = jobs[k - 2];
+            const bool with_side = has_t && ua < U;
+            ProgBuilder b(N, (int64_t)jb.nb * N);
+            b.p.n_iter = jb.m;
+            for (int j = 0; j < jb.m; ++j) b.p.weight[j] = weight[jb.j0 + j];
+            if (with_side) {
+                b.op(ROP_SIDE_T);
+                side(b.p.side, ua, U, sc.fft_y, sc.side_y);
+            }
+            b.op(ROP_LOOP)
+                .op(ROP_LOAD_C, W2[(k - 2) % 2], nn(N), N, (int64_t)jb.nb * nn(N))
+                .op(ROP_FFT_FWD)
+                .op(ROP_MUL_TAB, H[(k - 2) % 3], 0, 0, N)
+                .op(ROP_FFT_INV)
+                .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, RF_ITER_WEIGHT)
+                .op(ROP_ENDLOOP)
+                .op(ROP_STORE_ACC, Iacc, nn(N), N, 0, jb.j0 > 0 ? RF_ADD : 0);
+            const int rc = with_side ? run_row_side<ProgPropIntensityTTag>(N, b.p, b.n, stream)
+                                     : run_row<ProgPropIntensityTag>(PS_F32, N, b.p, b.n, stream);
+            if (rc) return rc;
+            if (jb.j0 + jb.m >= n_lambda) {
+                char *I = static_cast<char *>(I_out) + (size_t)jb.b0 * rb1;
+                if (int rc2 = transpose(Iacc, I, N, jb.nb, 4, stream)) return rc2;
+            }
+        }
+        if (!has_x && !has_y && has_t)
+            if (int rc = transpose(W1[t % 2], W2[t % 2], N, (int64_t)jobs[t].nb * jobs[t].m, 8, stream)) return rc;
+    }
+    return PS_OK;
+}
+
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref, double lambda_ref,
                                const double *lambdas, const double *weights, int n_lambda, int n_real, int dtype,
                                void *I_out, void *hip_stream) {
@@ -945,6 +1135,27 @@ int illumination_polychromatic(int N, double delta, double z, const void *phi_re
     const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
     const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
     const size_t budget = workspace_budget();
+    // FP32 from 2048 up: the pipelined form when four complex buffers of
+    // Cp*nb grids fit and there are at least two jobs
+    const SideCfg sc = side_cfg();
+    if (dtype == PS_F32 && N >= 2048 && sc.on) {
+        int Cp = std::min(n_lambda, kRowMaxIter);
+        auto need = [&](int Cq, int nbq) {
+            return 4 * cbytes * (size_t)Cq * nbq + rb1 * nbq + 3 * (size_t)Cq * N * 8 + 4096;
+        };
+        while (Cp > 1 && need(Cp, 1) > budget) Cp = (Cp + 1) / 2;
+        if (need(Cp, 1) <= budget) {
+            int nbp = 1;
+            while (nbp < n_real && need(Cp, nbp + 1) <= budget) ++nbp;
+            std::vector<PolyJob> jobs;
+            for (int b0 = 0; b0 < n_real; b0 += nbp)
+                for (int j0 = 0; j0 < n_lambda; j0 += Cp)
+                    jobs.push_back({b0, std::min(nbp, n_real - b0), j0, std::min(Cp, n_lambda - j0)});
+            if (jobs.size() >= 2)
+                return poly_pipelined(N, static_cast<const char *>(phi_ref), jobs, Cp, nbp, n_lambda, rho, scale,
+                                      weight, I_out, sc, stream);
+        }
+    }
     // wavelengths per pass C (<= 64) and realisations per pass nb so that two
     // complex buffers of C*nb grids plus the accumulator fit the budget
     int C = std::min(n_lambda, kRowMaxIter);

@@ -57,6 +57,7 @@ SIGNATURES = {
     "ps_num_plan_variants": (_c_int, [_c_int, _c_int]),
     "ps_plan_variant": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_float)]),
     "ps_set_plan_variant": (_c_int, [_c_int, _c_int, _c_int]),
+    "ps_set_workspace_budget": (_c_int, [ctypes.c_size_t]),
     "ps_timing_enable": (_c_int, [_c_int]),
     "ps_timing_count": (_c_int, []),
     "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp,
@@ -173,6 +174,13 @@ def plan_variant(N: int, dtype: torch.dtype = torch.float32):
 def set_plan_variant(N: int, variant: int, dtype: torch.dtype = torch.float32) -> None:
     """Pin FFT plan `variant` for size N (-1: back to the tuner's choice)."""
     _check("ps_set_plan_variant", load_library().ps_set_plan_variant(int(N), _dtype_code(dtype), int(variant)))
+
+
+def set_workspace_budget(nbytes: int, device=None) -> None:
+    """Cap the workspace the library plans for on `device` (default: the
+    current one) at nbytes; 0 restores the default."""
+    with torch.cuda.device(torch.device("cuda") if device is None else torch.device(device)):
+        _check("ps_set_workspace_budget", load_library().ps_set_workspace_budget(int(nbytes)))
 
 
 def timing_enable(on: bool = True) -> None:

@@ -1,0 +1,146 @@
+"""GPU parity of the pipelined polychromatic propagation (Sect. 3.2.4, Eq.
+phiNl): from N = 2048 up in FP32, with two or more jobs, the transpose
+between the x and y passes of one job runs as extra workgroups of the
+neighbouring jobs' row passes.
+
+The pipelined path must give the plain chunk loop's result bit for bit when
+both split the work into the same jobs; the workspace budgets below are
+chosen so that they do (comments give the job split).  Against the FP64
+oracle the usual FP32 bar holds (RMS 2e-5, max 1e-3 of the mean).
+
+Cases: many jobs of two wavelengths; a ragged last wavelength chunk; ragged
+transpose units (N = 4000 is not a multiple of 128 or 64) with 200-thread
+row workgroups, and 128-thread ones (4096, plan 0), where threads take two
+lane roles of the transpose; the bench's shape (8192, 32 wavelengths, two realisations: two
+jobs); the pipeline's prologue and epilogue with two and three jobs.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+F32_RMS, F32_MAX = 2e-5, 1e-3
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1301_0514_amd import scint
+    scint.load_library()
+    return scint
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1301_0514_amd import presets
+    return presets
+
+
+def poly(S, monkeypatch, phi, z, lam_ref, lams, w, budget, pipeline):
+    monkeypatch.setenv("SCINT_PIPELINE", "1" if pipeline else "0")
+    S.set_workspace_budget(budget)
+    try:
+        out = S.illumination_polychromatic(phi, 1.0, z, lam_ref, lams, w)
+        torch.cuda.synchronize()
+        return out
+    finally:
+        S.set_workspace_budget(0)
+
+
+def geometry(N, n_lambda, seed):
+    lam_ref = 650e-9
+    rho_ref = N / 12.0
+    z = 2 * np.pi * rho_ref ** 2 / lam_ref
+    lams = list(np.linspace(400e-9, 900e-9, n_lambda))
+    w = list(np.random.default_rng(seed).uniform(0.5, 2.0, n_lambda))
+    return z, lam_ref, lams, w
+
+
+# (N, n_real, n_lambda, pipelined budget, plain budget): both give jobs of
+#   2048: Cp = C = 2 wavelengths, one realisation (12 jobs; 6 jobs of 2, 2, 1)
+#   4000: one wavelength, one realisation (6 jobs)
+#   4096: one wavelength, one realisation (4 jobs)
+CASES = [(2048, 3, 8, 300 * MiB, 150 * MiB), (2048, 2, 5, 300 * MiB, 150 * MiB),
+         (4000, 2, 3, 600 * MiB, 330 * MiB), (4096, 2, 2, 600 * MiB, 330 * MiB)]
+
+
+@pytest.mark.parametrize("N,n_real,n_lambda,bp,bq", CASES)
+def test_pipelined_equals_plain(S, monkeypatch, N, n_real, n_lambda, bp, bq):
+    z, lam_ref, lams, w = geometry(N, n_lambda, N + n_lambda)
+    if N == 4096:
+        S.set_plan_variant(N, 0)  # the 128-thread plan
+    try:
+        phi = S.ps_generate(N, 1.0, N / 300.0, 11 / 3, 5, 0, n_real)
+        a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, bp, True)
+        b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, bq, False)
+    finally:
+        if N == 4096:
+            S.set_plan_variant(N, -1)
+    assert torch.equal(a, b)
+    assert float(a.mean()) == pytest.approx(1.0, abs=1e-5)
+
+
+@pytest.mark.parametrize("N,n_real,n_lambda,bp", [(2048, 2, 5, 300 * MiB), (4000, 1, 3, 600 * MiB)])
+def test_pipelined_vs_oracle(S, oracle, monkeypatch, N, n_real, n_lambda, bp):
+    z, lam_ref, lams, w = geometry(N, n_lambda, 3)
+    phi = np.stack([oracle.screen(N, N / 300.0, 11 / 3, 8, r) for r in range(n_real)])
+    phi32 = phi.astype(np.float32)
+    I = poly(S, monkeypatch, torch.tensor(phi32, device="cuda"), z, lam_ref, lams, w, bp, True)
+    I = I.double().cpu().numpy()
+    for b in range(n_real):
+        ref = oracle.polychromatic(phi32[b].astype(np.float64), 1.0, z, lam_ref, lams, w)
+        m = ref.mean()
+        d = I[b] - ref
+        e_rms, e_max = np.sqrt(np.mean(d * d)) / m, np.abs(d).max() / m
+        print("N=%d realisation %d e_rms=%.2e e_max=%.2e" % (N, b, e_rms, e_max))
+        assert e_rms < F32_RMS and e_max < F32_MAX
+
+
+@pytest.mark.parametrize("n_real", [2, 3])
+def test_pipeline_prologue_and_epilogue(S, monkeypatch, n_real):
+    # two jobs: the transpose of job 0 rides wholly on the x pass of job 1 and
+    # that of job 1 wholly on the y pass of job 0; three jobs add one split
+    N, n_lambda = 2048, 2
+    z, lam_ref, lams, w = geometry(N, n_lambda, 1)
+    phi = S.ps_generate(N, 1.0, 7.0, 11 / 3, 2, 0, n_real)
+    a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 300 * MiB, True)   # jobs: one realisation, 2 wavelengths
+    b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 150 * MiB, False)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("split,groups", [("0", None), ("1", None), ("0.3", "3:1:5:2"), (None, "1:1:1:1")])
+def test_pipeline_split_settings(S, monkeypatch, split, groups):
+    # every share and interleaving of the side transposes gives the same result
+    N, n_real, n_lambda = 2048, 3, 4
+    z, lam_ref, lams, w = geometry(N, n_lambda, 2)
+    phi = S.ps_generate(N, 1.0, 7.0, 11 / 3, 4, 0, n_real)
+    ref = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 150 * MiB, False)
+    if split is not None:
+        monkeypatch.setenv("SCINT_SIDE_SPLIT", split)
+    if groups is not None:
+        monkeypatch.setenv("SCINT_SIDE_GROUPS", groups)
+    a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 300 * MiB, True)
+    assert torch.equal(a, ref)
+
+
+def test_pipeline_bench_shape(S, P, monkeypatch):
+    # the bench's polychromatic configuration with two realisations: the
+    # pipelined path takes two jobs (64 GiB of workspace), the plain loop one
+    c = P.POLY_8192
+    N = c.N
+    phi = S.ps_generate(N, 1.0, c.R_ref, c.beta, c.seed, 0, 2)
+    GiB = 1 << 30
+    a = poly(S, monkeypatch, phi, c.z, c.lam_ref, c.lambdas, None, 70 * GiB, True)   # jobs: one realisation each
+    b = poly(S, monkeypatch, phi, c.z, c.lam_ref, c.lambdas, None, 70 * GiB, False)  # one job of both
+    assert torch.equal(a, b)
+    m = S.ps_modulation_index(a)
+    assert all(0.05 < x < 1.5 for x in m)
+
+
+def test_workspace_budget_rejects_tiny_values(S):
+    with pytest.raises(S.ScintError):
+        S.set_workspace_budget(1 << 20)
+    S.set_workspace_budget(0)
