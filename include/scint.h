@@ -138,11 +138,12 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
  *   phi_ref   device [n_real][N][N] real;  I_out device [n_real][N][N] real
  * Work is split into jobs of up to 64 wavelengths and as many realisations as
  * the workspace budget allows (ps_set_workspace_budget).  In FP32 from
- * N = 2048 up, with two or more jobs, the jobs are pipelined: the transpose
- * between the two 1-D passes of one job runs inside the launches of the
- * neighbouring jobs' passes, which takes twice the workspace of the plain
- * loop and gives the same result bit for bit for the same job split
- * (environment SCINT_PIPELINE=0 turns it off).
+ * N = 2048 up the jobs are pipelined (work that fits one job is split into
+ * two, by realisations or else by wavelengths): the transpose between the
+ * two 1-D passes of one job runs inside the launches of the neighbouring
+ * jobs' passes, which takes twice the workspace of the plain loop and gives
+ * the same result bit for bit for the same job split (environment
+ * SCINT_PIPELINE=0 turns it off).
  */
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref,
                                double lambda_ref, const double *lambdas,

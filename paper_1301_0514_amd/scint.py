@@ -179,6 +179,8 @@ def set_plan_variant(N: int, variant: int, dtype: torch.dtype = torch.float32) -
 def set_workspace_budget(nbytes: int, device=None) -> None:
     """Cap the workspace the library plans for on `device` (default: the
     current one) at nbytes; 0 restores the default."""
+    if int(nbytes) < 0:
+        raise ValueError("nbytes must be >= 0")
     with torch.cuda.device(torch.device("cuda") if device is None else torch.device(device)):
         _check("ps_set_workspace_budget", load_library().ps_set_workspace_budget(int(nbytes)))
 

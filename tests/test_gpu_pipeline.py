@@ -61,10 +61,12 @@ def geometry(N, n_lambda, seed):
 
 # (N, n_real, n_lambda, pipelined budget, plain budget): both give jobs of
 #   2048: Cp = C = 2 wavelengths, one realisation (12 jobs; 6 jobs of 2, 2, 1)
+#   2048 x 5 realisations: two wavelengths, two realisations (jobs of 2, 2, 1)
 #   4000: one wavelength, one realisation (6 jobs)
 #   4096: one wavelength, one realisation (4 jobs)
 CASES = [(2048, 3, 8, 300 * MiB, 150 * MiB), (2048, 2, 5, 300 * MiB, 150 * MiB),
-         (4000, 2, 3, 600 * MiB, 330 * MiB), (4096, 2, 2, 600 * MiB, 330 * MiB)]
+         (2048, 5, 2, 600 * MiB, 300 * MiB), (4000, 2, 3, 600 * MiB, 330 * MiB),
+         (4096, 2, 2, 600 * MiB, 330 * MiB)]
 
 
 @pytest.mark.parametrize("N,n_real,n_lambda,bp,bq", CASES)
@@ -143,6 +145,8 @@ def test_pipeline_bench_shape(S, P, monkeypatch):
 def test_workspace_budget_rejects_tiny_values(S):
     with pytest.raises(S.ScintError):
         S.set_workspace_budget(1 << 20)
+    with pytest.raises(ValueError):
+        S.set_workspace_budget(-1)
     S.set_workspace_budget(0)
 
 
@@ -182,3 +186,30 @@ def test_pipeline_graph_replay_matches_eager(S):
         assert torch.equal(ext, ref_ext), rep
         S.ps_screen_fresnel(128, 1.0, 3.0, 11 / 3, 1, 5e-7, 1e4)
         torch.cuda.synchronize()
+
+
+def test_single_job_work_is_split_in_two(S, monkeypatch):
+    # work that fits one job runs as two pipelined jobs: by realisations
+    # (the same sums as the plain loop, so the same bits) ...
+    N = 2048
+    z, lam_ref, lams, w = geometry(N, 4, 7)
+    phi = S.ps_generate(N, 1.0, 7.0, 11 / 3, 3, 0, 3)
+    a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, True)
+    b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, False)
+    assert torch.equal(a, b)
+
+
+def test_single_realisation_split_by_wavelength(S, oracle, monkeypatch):
+    # ... or, for one realisation, by wavelengths (two partial sums: equal to
+    # the plain loop to FP32 rounding, and within the bar of the oracle)
+    N = 2048
+    z, lam_ref, lams, w = geometry(N, 5, 8)
+    phi = oracle.screen(N, 7.0, 11 / 3, 3, 0).astype(np.float32)
+    phit = torch.tensor(phi[None], device="cuda")
+    a = poly(S, monkeypatch, phit, z, lam_ref, lams, w, 0, True)
+    b = poly(S, monkeypatch, phit, z, lam_ref, lams, w, 0, False)
+    assert float((a - b).abs().max()) <= 4e-6 * float(b.abs().max())
+    ref = oracle.polychromatic(phi.astype(np.float64), 1.0, z, lam_ref, lams, w)
+    d = a[0].double().cpu().numpy() - ref
+    m = ref.mean()
+    assert np.sqrt(np.mean(d * d)) / m < F32_RMS and np.abs(d).max() / m < F32_MAX
