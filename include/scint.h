@@ -112,6 +112,8 @@ int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed,
  *
  *   phi       device [n][N][N] real (input, not modified)
  *   I_out     device [n][N][N] real; must not overlap phi (PS_E_ALIAS)
+ * In FP32 from N = 2048 up with n >= 2 the screens run as the pipelined jobs
+ * of illumination_polychromatic (one wavelength), with the same result.
  */
 int fresnel_propagate(int N, double delta, double lambda, double z, const void *phi,
                       double phase_scale, int n, int dtype, void *I_out, void *hip_stream);

@@ -851,121 +851,6 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
     return run_row<ProgPropIntensityTag>(dtype, N, b.p, b.n, stream);
 }
 
-int fresnel_propagate(int N, double delta, double lambda, double z, const void *phi, double phase_scale, int n,
-                      int dtype, void *I_out, void *hip_stream) {
-    g_last_error.clear();
-    g_last_warning.clear();
-    if (int rc = check_common(N, dtype, n)) return rc;
-    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
-    if (int rc = check_aligned({phi, I_out})) return rc;
-    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
-        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
-    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
-    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
-    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
-    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
-    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
-    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
-    for (int b0 = 0; b0 < n; b0 += nb_max) {
-        const int nb = std::min(nb_max, n - b0);
-        void *ws = nullptr;
-        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
-        Carver c;
-        char *base = static_cast<char *>(ws);
-        void *W1 = base + c.take(cbytes * nb);
-        void *W2 = base + c.take(cbytes * nb);
-        void *H = base + c.take(tbytes);
-        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
-        // W1 (complex) is free again once transposed into W2, so it holds the
-        // transposed intensity
-        if (int rc = poly_chunk(N, ph, nb, {rho}, {phase_scale}, {1.0}, dtype, W1, W2, H, W1, false, stream))
-            return rc;
-        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
-        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
-    }
-    return PS_OK;
-}
-
-int fresnel_aperture(int N, double delta, double lambda, double z, const void *phi, double phase_scale,
-                     double margin_rf, int n, int dtype, void *I_out, void *hip_stream) {
-    g_last_error.clear();
-    g_last_warning.clear();
-    if (int rc = check_common(N, dtype, n)) return rc;
-    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
-    if (int rc = check_aligned({phi, I_out})) return rc;
-    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
-        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
-    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
-    if (!(std::isfinite(margin_rf) && margin_rf >= 0.0)) return fail(PS_E_PARAM, "margin_rf must be finite and >= 0");
-    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
-    const double two_pi_rho2 = 2.0 * kPiD * rho * rho;
-    if ((double)N > two_pi_rho2 * (1.0 + 1e-9))
-        return fail(PS_E_PARAM, "N delta^2 > lambda z: the Fresnel chirp is undersampled at the screen border");
-    const double Lm = margin_rf * rho;
-    if (2.0 * Lm > (double)N) return fail(PS_E_PARAM, "the window margins (2 margin_rf R_F) exceed the screen");
-    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
-    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
-    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
-    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
-    const double norm = 1.0 / (two_pi_rho2 * two_pi_rho2);
-    for (int b0 = 0; b0 < n; b0 += nb_max) {
-        const int nb = std::min(nb_max, n - b0);
-        void *ws = nullptr;
-        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
-        Carver c;
-        char *base = static_cast<char *>(ws);
-        void *W1 = base + c.take(cbytes * nb);
-        void *W2 = base + c.take(cbytes * nb);
-        void *A = base + c.take(tbytes);
-        HIP_TRY(launch_aperture_table(A, N, 1.0 / (4.0 * kPiD * rho * rho), Lm, dtype == PS_F64, stream));
-        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
-        // rows y: G = A[x] A[y] exp(i s phi), DFT along x
-        ProgBuilder a(N, (int64_t)nb * N);
-        a.op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
-            .op(ROP_MUL_TAB, A)
-            .op(ROP_MUL_ROWTAB, A)
-            .op(ROP_FFT_FWD)
-            .op(ROP_STORE_C, W1, nn(N), N);
-        if (int rc = run_row<ProgApertureXTag>(dtype, N, a.p, a.n, stream)) return rc;
-        if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
-        // rows kx: DFT along y, |.|^2 / (2 pi rho^2)^2 (transposed intensity in W1)
-        ProgBuilder d(N, (int64_t)nb * N);
-        d.op(ROP_LOAD_C, W2, nn(N), N)
-            .op(ROP_FFT_FWD)
-            .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, norm)
-            .op(ROP_STORE_ACC, W1, nn(N), N);
-        if (int rc = run_row<ProgAbs2Tag>(dtype, N, d.p, d.n, stream)) return rc;
-        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
-        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
-    }
-    return PS_OK;
-}
-
-int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_diff, double r_s,
-                         double *observer_pixel, int *fiducial_margin) {
-    g_last_error.clear();
-    g_last_warning.clear();
-    if (N < 2) return fail(PS_E_SIZE, "N must be >= 2");
-    if (!observer_pixel || !fiducial_margin) return fail(PS_E_NULL, "observer_pixel and fiducial_margin must be non-NULL");
-    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z) || !finite_pos(r_diff))
-        return fail(PS_E_PARAM, "delta, lambda, z and r_diff must be finite and > 0");
-    if (!(std::isfinite(r_s) && r_s >= 0.0)) return fail(PS_E_PARAM, "r_s must be finite and >= 0");
-    const double pix0 = lambda * z / ((double)N * delta);
-    const double r_ref = lambda * z / r_diff;  // 2 pi R_F^2 / R_diff
-    // the illuminated pattern is the screen's shadow, N delta wide, centred on
-    // the observer grid (N pix0 wide, pix0 >= delta when fresnel_aperture runs)
-    const double rim = std::max(0.0, 0.5 * (double)N * (1.0 - delta / pix0));
-    const double m = std::ceil(rim + (0.5 * r_ref + r_s) / pix0 - 1e-9);
-    *observer_pixel = pix0;
-    *fiducial_margin = m > (double)N ? N : (int)m;
-    if (2.0 * m >= (double)N) g_last_warning = "the fiducial zone is empty at this geometry";
-    return PS_OK;
-}
-
 // Interleaving of the pipelined propagation below: the share of each job's
 // transpose units carried by the next job's x pass (the rest rides on the y
 // pass two jobs back), and per pass the row workgroups and transpose
@@ -1104,6 +989,164 @@ static int poly_pipelined(int N, const char *phi_ref, const std::vector<PolyJob>
     return PS_OK;
 }
 
+// Jobs of the pipelined propagation (FP32): up to 64 wavelengths and as many
+// realisations per job as four complex buffers of the job's grids fit the
+// budget; work that fits one job is split in two (realisations, else
+// wavelengths): two pipelined jobs beat one plain job by ~10 % at 2048^2 and
+// 4096^2 (8 realisations x 32 wavelengths), more jobs than the memory needs do
+// not gain further.  False if the work does not make two jobs or one job does
+// not fit.
+static bool plan_poly_jobs(int N, int n_real, int n_lambda, size_t budget, std::vector<PolyJob> *jobs, int *Cp_out,
+                           int *nbp_out) {
+    const size_t cbytes = (size_t)nn(N) * 8, rb1 = (size_t)nn(N) * 4;
+    auto need = [&](int Cq, int nbq) {
+        return 4 * cbytes * (size_t)Cq * nbq + rb1 * nbq + 3 * (size_t)Cq * N * 8 + 4096;
+    };
+    int Cp = std::min(n_lambda, kRowMaxIter);
+    while (Cp > 1 && need(Cp, 1) > budget) Cp = (Cp + 1) / 2;
+    if (need(Cp, 1) > budget) return false;
+    int nbp = 1;
+    while (nbp < n_real && need(Cp, nbp + 1) <= budget) ++nbp;
+    if (nbp >= n_real && Cp >= n_lambda) {
+        if (n_real >= 2)
+            nbp = (n_real + 1) / 2;
+        else
+            Cp = (n_lambda + 1) / 2;
+    }
+    jobs->clear();
+    for (int b0 = 0; b0 < n_real; b0 += nbp)
+        for (int j0 = 0; j0 < n_lambda; j0 += Cp)
+            jobs->push_back({b0, std::min(nbp, n_real - b0), j0, std::min(Cp, n_lambda - j0)});
+    *Cp_out = Cp;
+    *nbp_out = nbp;
+    return jobs->size() >= 2;
+}
+
+int fresnel_propagate(int N, double delta, double lambda, double z, const void *phi, double phase_scale, int n,
+                      int dtype, void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
+    if (int rc = check_aligned({phi, I_out})) return rc;
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
+    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    // FP32 from 2048 up with two or more realisations: the pipelined form
+    // (one wavelength of phase scale s and weight 1)
+    const SideCfg sc = side_cfg();
+    if (dtype == PS_F32 && N >= 2048 && n >= 2 && sc.on) {
+        std::vector<PolyJob> jobs;
+        int Cp = 0, nbp = 0;
+        if (plan_poly_jobs(N, n, 1, workspace_budget(), &jobs, &Cp, &nbp))
+            return poly_pipelined(N, static_cast<const char *>(phi), jobs, Cp, nbp, 1, {rho}, {phase_scale}, {1.0},
+                                  I_out, sc, stream);
+    }
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        void *H = base + c.take(tbytes);
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        // W1 (complex) is free again once transposed into W2, so it holds the
+        // transposed intensity
+        if (int rc = poly_chunk(N, ph, nb, {rho}, {phase_scale}, {1.0}, dtype, W1, W2, H, W1, false, stream))
+            return rc;
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
+    return PS_OK;
+}
+
+int fresnel_aperture(int N, double delta, double lambda, double z, const void *phi, double phase_scale,
+                     double margin_rf, int n, int dtype, void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
+    if (int rc = check_aligned({phi, I_out})) return rc;
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    if (!(std::isfinite(margin_rf) && margin_rf >= 0.0)) return fail(PS_E_PARAM, "margin_rf must be finite and >= 0");
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const double two_pi_rho2 = 2.0 * kPiD * rho * rho;
+    if ((double)N > two_pi_rho2 * (1.0 + 1e-9))
+        return fail(PS_E_PARAM, "N delta^2 > lambda z: the Fresnel chirp is undersampled at the screen border");
+    const double Lm = margin_rf * rho;
+    if (2.0 * Lm > (double)N) return fail(PS_E_PARAM, "the window margins (2 margin_rf R_F) exceed the screen");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
+    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    const double norm = 1.0 / (two_pi_rho2 * two_pi_rho2);
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        void *A = base + c.take(tbytes);
+        HIP_TRY(launch_aperture_table(A, N, 1.0 / (4.0 * kPiD * rho * rho), Lm, dtype == PS_F64, stream));
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        // rows y: G = A[x] A[y] exp(i s phi), DFT along x
+        ProgBuilder a(N, (int64_t)nb * N);
+        a.op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
+            .op(ROP_MUL_TAB, A)
+            .op(ROP_MUL_ROWTAB, A)
+            .op(ROP_FFT_FWD)
+            .op(ROP_STORE_C, W1, nn(N), N);
+        if (int rc = run_row<ProgApertureXTag>(dtype, N, a.p, a.n, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
+        // rows kx: DFT along y, |.|^2 / (2 pi rho^2)^2 (transposed intensity in W1)
+        ProgBuilder d(N, (int64_t)nb * N);
+        d.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, norm)
+            .op(ROP_STORE_ACC, W1, nn(N), N);
+        if (int rc = run_row<ProgAbs2Tag>(dtype, N, d.p, d.n, stream)) return rc;
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
+    return PS_OK;
+}
+
+int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_diff, double r_s,
+                         double *observer_pixel, int *fiducial_margin) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (N < 2) return fail(PS_E_SIZE, "N must be >= 2");
+    if (!observer_pixel || !fiducial_margin) return fail(PS_E_NULL, "observer_pixel and fiducial_margin must be non-NULL");
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z) || !finite_pos(r_diff))
+        return fail(PS_E_PARAM, "delta, lambda, z and r_diff must be finite and > 0");
+    if (!(std::isfinite(r_s) && r_s >= 0.0)) return fail(PS_E_PARAM, "r_s must be finite and >= 0");
+    const double pix0 = lambda * z / ((double)N * delta);
+    const double r_ref = lambda * z / r_diff;  // 2 pi R_F^2 / R_diff
+    // the illuminated pattern is the screen's shadow, N delta wide, centred on
+    // the observer grid (N pix0 wide, pix0 >= delta when fresnel_aperture runs)
+    const double rim = std::max(0.0, 0.5 * (double)N * (1.0 - delta / pix0));
+    const double m = std::ceil(rim + (0.5 * r_ref + r_s) / pix0 - 1e-9);
+    *observer_pixel = pix0;
+    *fiducial_margin = m > (double)N ? N : (int)m;
+    if (2.0 * m >= (double)N) g_last_warning = "the fiducial zone is empty at this geometry";
+    return PS_OK;
+}
+
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref, double lambda_ref,
                                const double *lambdas, const double *weights, int n_lambda, int n_real, int dtype,
                                void *I_out, void *hip_stream) {
@@ -1139,32 +1182,11 @@ int illumination_polychromatic(int N, double delta, double z, const void *phi_re
     // Cp*nb grids fit and the work makes at least two jobs
     const SideCfg sc = side_cfg();
     if (dtype == PS_F32 && N >= 2048 && sc.on) {
-        int Cp = std::min(n_lambda, kRowMaxIter);
-        auto need = [&](int Cq, int nbq) {
-            return 4 * cbytes * (size_t)Cq * nbq + rb1 * nbq + 3 * (size_t)Cq * N * 8 + 4096;
-        };
-        while (Cp > 1 && need(Cp, 1) > budget) Cp = (Cp + 1) / 2;
-        if (need(Cp, 1) <= budget) {
-            int nbp = 1;
-            while (nbp < n_real && need(Cp, nbp + 1) <= budget) ++nbp;
-            // work that fits one job is split in two (realisations, else
-            // wavelengths): two pipelined jobs beat one plain job by ~10 % at
-            // 2048^2 and 4096^2 (8 realisations x 32 wavelengths), more jobs
-            // than the memory needs do not gain further
-            if (nbp >= n_real && Cp >= n_lambda) {
-                if (n_real >= 2)
-                    nbp = (n_real + 1) / 2;
-                else
-                    Cp = (n_lambda + 1) / 2;
-            }
-            std::vector<PolyJob> jobs;
-            for (int b0 = 0; b0 < n_real; b0 += nbp)
-                for (int j0 = 0; j0 < n_lambda; j0 += Cp)
-                    jobs.push_back({b0, std::min(nbp, n_real - b0), j0, std::min(Cp, n_lambda - j0)});
-            if (jobs.size() >= 2)
-                return poly_pipelined(N, static_cast<const char *>(phi_ref), jobs, Cp, nbp, n_lambda, rho, scale,
-                                      weight, I_out, sc, stream);
-        }
+        std::vector<PolyJob> jobs;
+        int Cp = 0, nbp = 0;
+        if (plan_poly_jobs(N, n_real, n_lambda, budget, &jobs, &Cp, &nbp))
+            return poly_pipelined(N, static_cast<const char *>(phi_ref), jobs, Cp, nbp, n_lambda, rho, scale, weight,
+                                  I_out, sc, stream);
     }
     // wavelengths per pass C (<= 64) and realisations per pass nb so that two
     // complex buffers of C*nb grids plus the accumulator fit the budget

@@ -213,3 +213,18 @@ def test_single_realisation_split_by_wavelength(S, oracle, monkeypatch):
     d = a[0].double().cpu().numpy() - ref
     m = ref.mean()
     assert np.sqrt(np.mean(d * d)) / m < F32_RMS and np.abs(d).max() / m < F32_MAX
+
+
+@pytest.mark.parametrize("N,n", [(2048, 3), (4000, 2)])
+def test_fresnel_propagate_pipelined_equals_plain(S, monkeypatch, N, n):
+    # fresnel_propagate with several realisations takes the same pipeline
+    # (one wavelength); its result is the plain loop's, bit for bit
+    phi = S.ps_generate(N, 1.0, N / 300.0, 11 / 3, 6, 0, n)
+    lam, s = 5e-7, 0.8
+    z = 2 * np.pi * (N / 12.0) ** 2 / lam
+    monkeypatch.setenv("SCINT_PIPELINE", "1")
+    a = S.fresnel_propagate(phi, 1.0, lam, z, s)
+    monkeypatch.setenv("SCINT_PIPELINE", "0")
+    b = S.fresnel_propagate(phi, 1.0, lam, z, s)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
