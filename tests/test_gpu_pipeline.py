@@ -228,3 +228,17 @@ def test_fresnel_propagate_pipelined_equals_plain(S, monkeypatch, N, n):
     b = S.fresnel_propagate(phi, 1.0, lam, z, s)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("N", [10000, 16384])
+def test_pipelined_equals_plain_large_workgroups(S, monkeypatch, N):
+    # row workgroups of 1000 (10000, ragged transpose units) and 512 threads
+    # (16384): threads beyond 256 only take part in the side transposes'
+    # barriers.  Default budget: two pipelined jobs of one realisation against
+    # one plain job of both, the same sums
+    z, lam_ref, lams, w = geometry(N, 2, 4)
+    phi = S.ps_generate(N, 1.0, N / 300.0, 11 / 3, 12, 0, 2)
+    a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, True)
+    b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, False)
+    assert torch.equal(a, b)
+    assert float(a.mean()) == pytest.approx(1.0, abs=1e-5)
