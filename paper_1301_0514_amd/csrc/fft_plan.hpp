@@ -53,7 +53,7 @@ SCINT_PLAN(512, 8, 8, 8, 8)
 SCINT_PLAN(1024, 16, 16, 16, 4)
 SCINT_PLAN(2048, 16, 16, 16, 8)
 SCINT_PLAN(4096, 32, 32, 8, 16)
-SCINT_PLAN(8192, 32, 32, 32, 8)
+SCINT_PLAN(8192, 32, 32, 8, 32)
 SCINT_PLAN(16384, 32, 32, 32, 16)
 // 2^a 5^b
 SCINT_PLAN(40, 20, 4, 10)
@@ -81,7 +81,7 @@ SCINT_PLAN_V(2048, 1, 16, 16, 8, 16)
 SCINT_PLAN_V(4096, 1, 16, 16, 16, 16)
 SCINT_PLAN_V(4096, 2, 32, 32, 16, 8)
 SCINT_PLAN_V(8192, 1, 16, 16, 8, 8, 8)
-SCINT_PLAN_V(8192, 2, 32, 32, 8, 32)
+SCINT_PLAN_V(8192, 2, 32, 32, 32, 8)
 SCINT_PLAN_V(10000, 1, 20, 20, 20, 5, 5)
 SCINT_PLAN_V(16384, 1, 32, 16, 32, 32)
 SCINT_PLAN_V(16384, 2, 32, 32, 16, 32)
