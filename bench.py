@@ -54,10 +54,10 @@ def source_hash(kernel: str = "row_") -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str, plan_variant: int | None = None):
-    """HBM bytes per launch of `kernel` from a committed rocprofv3 --pmc
-    summary (profiles/traffic_*.txt), if it was taken on the current kernel
-    sources and, for row passes, FFT plan variant."""
+def stored_profile(kernel: str, plan_variant: int | None = None) -> dict:
+    """The key = value lines of the committed rocprofv3 --pmc summary of
+    `kernel` (profiles/traffic_*.txt), if it was taken on the current kernel
+    sources and, for row passes, FFT plan variant; else {}."""
     want = source_hash(kernel)
     if not kernel.startswith("row_"):
         plan_variant = None
@@ -71,11 +71,25 @@ def stored_traffic(kernel: str, plan_variant: int | None = None):
         if plan_variant is not None and vals.get("plan_variant") not in (None, str(plan_variant)):
             continue
         if vals.get("kernel") == kernel and vals.get("source_sha256") == want:
-            try:
-                return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
-            except (KeyError, ValueError):
-                return None
-    return None
+            return vals
+    return {}
+
+
+def stored_traffic(kernel: str, plan_variant: int | None = None):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated)
+    from its stored profile, or None."""
+    vals = stored_profile(kernel, plan_variant)
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def stored_float(kernel: str, key: str, plan_variant: int | None = None):
+    try:
+        return float(stored_profile(kernel, plan_variant)[key])
+    except (KeyError, ValueError):
+        return None
 
 
 def main(argv=None) -> int:
@@ -192,6 +206,11 @@ def main(argv=None) -> int:
     except (IndexError, ValueError, scint.ScintError):
         dom_variant = None
     traffic = stored_traffic(dname, dom_variant)
+    # the other two ceilings from the stored SQ counters of the same kernel:
+    # VALU issue (wave64 instructions x 4 cycles over 1024 SIMDs x active
+    # cycles) and LDS bank conflicts per LDS-active cycle
+    valu_issue = stored_float(dname, "valu_issue_frac", dom_variant)
+    lds_conflict = stored_float(dname, "lds_bank_conflict_frac", dom_variant)
     kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                    "avg_launch_ms": v["ms"] / v["launches"],
                    "algorithmic_GBps": (v["bytes"] / v["launches"]) / (v["ms"] / v["launches"] / 1e3) / 1e9,
@@ -215,6 +234,8 @@ def main(argv=None) -> int:
         if flops_per_launch > 0:
             roofline.update({"algorithmic_flops_per_launch": flops_per_launch, "alu_achieved_TFLOPs": tflops,
                              "alu_frac": tflops / FP32_VECTOR_PEAK_TFLOPS})
+    roofline["valu_issue_frac"] = valu_issue
+    roofline["lds_bank_conflict_frac"] = lds_conflict
     # whole-step algorithmic bytes: the sum over kernels of their operands
     step_bytes = sum(v["bytes"] for v in rep.values()) / args.steps
 
