@@ -314,8 +314,9 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
  * FFT plan variants and the plan tuner.  The large FP32 sizes (2048, 4096,
  * 8192, 10000, 16384) have several compiled Stockham plans (radix orders and
  * elements per thread).  The first FP32 call of such a size on a device times
- * each plan on a propagation row pass over scratch data (hipMalloc of
- * <= 200 MB, a private stream, synchronised) and keeps the fastest; it keeps
+ * each plan on a propagation row pass of 32 wavelength iterations over
+ * scratch data (hipMalloc of about 200 MB, a private stream, synchronised)
+ * and keeps the fastest; it keeps
  * plan 0 unless another is faster by more than 3%.  Different plans round
  * differently (within FP32 rounding), so pin a plan for bitwise-reproducible
  * results across processes: environment SCINT_PLAN_VARIANT=<v> or

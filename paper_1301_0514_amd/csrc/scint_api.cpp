@@ -434,15 +434,17 @@ template <class Tag> int run_row_side(int N, const RowProgram &p, int n_ops, hip
 // ------------------------------------------------------------ plan tuner
 // The large FP32 sizes have several compiled Stockham plans (fft_plan.hpp).
 // On the first FP32 call of such a size on a device, each plan is timed on a
-// propagation row pass (FFT, chirp multiply, inverse FFT, |.|^2, 4 iterations)
-// over 1024 rows of scratch data, on a private stream; the fastest is kept,
+// propagation row pass (FFT, chirp multiply, inverse FFT, |.|^2, 32 iterations)
+// over 2^24 points of scratch data, on a private stream; the fastest is kept,
 // unless it beats plan 0 by less than 3% (stable choices across runs).
 // SCINT_PLAN_VARIANT=<v> in the environment, or ps_set_plan_variant, pins it.
 int tune_plan(int N, std::vector<float> *ms_out, int *best) {
     const int nv = plan_variants(N);
     // about 2^24 points per launch (several waves of workgroups at every
-    // size), four wavelength iterations
-    const int rows = std::max(1024, (1 << 24) / N), iters = 4;
+    // size) and 32 wavelength iterations, as in a polychromatic pass: with
+    // only 4, the once-per-workgroup setup (the LDS twiddle cache) weighed
+    // enough to rank near-equal plans against what the full passes measure
+    const int rows = std::max(1024, (1 << 24) / N), iters = 32;
     const size_t cb = (size_t)rows * N * 8;
     void *buf = nullptr;
     if (hipMalloc(&buf, cb + (size_t)rows * N * 4 + (size_t)iters * N * 8 + 1024) != hipSuccess)
