@@ -1392,8 +1392,6 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
     for (int b0 = 0; b0 < n; b0 += nb_max) {
         const int nb = std::min(nb_max, n - b0);
         void *ws = nullptr;
-        const int nblk_rows = 1;
-        (void)nblk_rows;
         if (int rc = get_workspace(stream, (2 * cbytes + rb1) * nb + tbytes + (size_t)nb * N * 8 + nb * 8 + 4096,
                                    &ws))
             return rc;
