@@ -184,9 +184,18 @@ template <int R, int S, typename Real> struct Dft {
             Dft<R1, S, Real>::run(b);
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
+                // W^e is 1, S i, -1 or -S i for e = 0, R/4, R/2, 3R/4: a swap
+                // and sign changes (a multiply by an exact 0 or 1 is not
+                // folded away under IEEE rules); other e a complex multiply
                 const int e = (n2 * k1) % R;
                 if (e == 0) {
                     y[n2 * R1 + k1] = b[k1];
+                } else if (4 * e == R) {
+                    y[n2 * R1 + k1] = mul_si<S>(b[k1]);
+                } else if (2 * e == R) {
+                    y[n2 * R1 + k1] = {-b[k1].re, -b[k1].im};
+                } else if (4 * e == 3 * R) {
+                    y[n2 * R1 + k1] = mul_si<-S>(b[k1]);
                 } else {
                     cpx<Real> w = {(Real)W.c[e], (Real)W.s[e]};
                     y[n2 * R1 + k1] = cmul(b[k1], w);
