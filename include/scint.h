@@ -344,6 +344,22 @@ int ps_set_plan_variant(int N, int dtype, int variant);
 int ps_set_workspace_budget(size_t bytes);
 
 /*
+ * ps_plan_polychromatic -- how illumination_polychromatic would split a call
+ * of these sizes under a workspace budget of budget_bytes (host arithmetic
+ * only: no device call, callable without a GPU).  Any output pointer may be
+ * NULL.
+ *   pipelined        1 if the jobs are pipelined (transposes inside the
+ *                    passes), 0 for the plain loop
+ *   n_jobs           number of jobs (pipelined) or chunks (plain loop)
+ *   lambdas_per_job  wavelengths per job (<= 64)
+ *   real_per_job     realisations per job
+ *   workspace_bytes  workspace the call asks for
+ * Errors as for illumination_polychromatic's sizes; budget_bytes must be > 0.
+ */
+int ps_plan_polychromatic(int N, int n_real, int n_lambda, int dtype, size_t budget_bytes, int *pipelined,
+                          int *n_jobs, int *lambdas_per_job, int *real_per_job, size_t *workspace_bytes);
+
+/*
  * Kernel timing (instrumentation).  While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the stream it runs on,
  * and per kernel name the library accumulates the event-measured duration,

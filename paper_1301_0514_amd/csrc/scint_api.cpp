@@ -1149,6 +1149,36 @@ int ps_aperture_geometry(int N, double delta, double lambda, double z, double r_
     return PS_OK;
 }
 
+// The split of a polychromatic call (also reported by ps_plan_polychromatic):
+// in FP32 from 2048 up, the pipelined jobs when four complex buffers of a
+// job's grids fit (and there are two or more); otherwise chunks of C <= 64
+// wavelengths and nb realisations such that two complex buffers of C nb
+// grids plus the accumulator fit the budget.
+struct PolyPlan {
+    bool pipelined = false;
+    int C = 1, nb = 1;
+    std::vector<PolyJob> jobs;  // pipelined jobs (empty for the plain loop)
+    size_t ws_bytes = 0;        // workspace it asks for
+};
+static PolyPlan plan_polychromatic(int N, int n_real, int n_lambda, int dtype, size_t budget, const SideCfg &sc) {
+    PolyPlan pl;
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
+    if (dtype == PS_F32 && N >= 2048 && sc.on &&
+        plan_poly_jobs(N, n_real, n_lambda, budget, &pl.jobs, &pl.C, &pl.nb)) {
+        pl.pipelined = true;
+        pl.ws_bytes = 4 * cbytes * (size_t)pl.C * pl.nb + rb1 * pl.nb + 3 * (size_t)pl.C * N * 8 + 4096;
+        return pl;
+    }
+    pl.jobs.clear();
+    int C = std::min(n_lambda, kRowMaxIter);
+    while (C > 1 && 2 * cbytes * (size_t)C + rb1 > budget) C = (C + 1) / 2;
+    pl.C = C;
+    pl.nb = std::min(n_real, (int)std::max<size_t>(1, budget / (2 * cbytes * (size_t)C + rb1)));
+    pl.ws_bytes = 2 * cbytes * (size_t)C * pl.nb + rb1 * pl.nb + (size_t)C * N * 2 * real_bytes(dtype) + 2048;
+    return pl;
+}
+
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref, double lambda_ref,
                                const double *lambdas, const double *weights, int n_lambda, int n_real, int dtype,
                                void *I_out, void *hip_stream) {
@@ -1179,22 +1209,12 @@ int illumination_polychromatic(int N, double delta, double z, const void *phi_re
     }
     const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
     const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
-    const size_t budget = workspace_budget();
-    // FP32 from 2048 up: the pipelined form when four complex buffers of
-    // Cp*nb grids fit and the work makes at least two jobs
     const SideCfg sc = side_cfg();
-    if (dtype == PS_F32 && N >= 2048 && sc.on) {
-        std::vector<PolyJob> jobs;
-        int Cp = 0, nbp = 0;
-        if (plan_poly_jobs(N, n_real, n_lambda, budget, &jobs, &Cp, &nbp))
-            return poly_pipelined(N, static_cast<const char *>(phi_ref), jobs, Cp, nbp, n_lambda, rho, scale, weight,
-                                  I_out, sc, stream);
-    }
-    // wavelengths per pass C (<= 64) and realisations per pass nb so that two
-    // complex buffers of C*nb grids plus the accumulator fit the budget
-    int C = std::min(n_lambda, kRowMaxIter);
-    while (C > 1 && 2 * cbytes * (size_t)C + rb1 > budget) C = (C + 1) / 2;
-    const int nb_max = (int)std::max<size_t>(1, budget / (2 * cbytes * (size_t)C + rb1));
+    const PolyPlan pl = plan_polychromatic(N, n_real, n_lambda, dtype, workspace_budget(), sc);
+    if (pl.pipelined)
+        return poly_pipelined(N, static_cast<const char *>(phi_ref), pl.jobs, pl.C, pl.nb, n_lambda, rho, scale, weight,
+                              I_out, sc, stream);
+    const int C = pl.C, nb_max = pl.nb;
     for (int b0 = 0; b0 < n_real; b0 += nb_max) {
         const int nb = std::min(nb_max, n_real - b0);
         void *ws = nullptr;
@@ -1217,6 +1237,23 @@ int illumination_polychromatic(int N, double delta, double z, const void *phi_re
         char *I = static_cast<char *>(I_out) + (size_t)b0 * rb1;
         if (int rc = transpose(Iacc, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
     }
+    return PS_OK;
+}
+
+int ps_plan_polychromatic(int N, int n_real, int n_lambda, int dtype, size_t budget_bytes, int *pipelined,
+                          int *n_jobs, int *lambdas_per_job, int *real_per_job, size_t *workspace_bytes) {
+    g_last_error.clear();
+    if (int rc = check_common(N, dtype, n_real)) return rc;
+    if (n_lambda < 1 || n_lambda > 4096) return fail(PS_E_SIZE, "n_lambda must lie in [1, 4096]");
+    if (budget_bytes == 0) return fail(PS_E_PARAM, "budget_bytes must be > 0");
+    const PolyPlan pl = plan_polychromatic(N, n_real, n_lambda, dtype, budget_bytes, side_cfg());
+    const int jobs = pl.pipelined ? (int)pl.jobs.size()
+                                  : ((n_real + pl.nb - 1) / pl.nb) * ((n_lambda + pl.C - 1) / pl.C);
+    if (pipelined) *pipelined = pl.pipelined ? 1 : 0;
+    if (n_jobs) *n_jobs = jobs;
+    if (lambdas_per_job) *lambdas_per_job = pl.C;
+    if (real_per_job) *real_per_job = pl.nb;
+    if (workspace_bytes) *workspace_bytes = pl.ws_bytes;
     return PS_OK;
 }
 

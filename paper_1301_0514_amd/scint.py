@@ -58,6 +58,9 @@ SIGNATURES = {
     "ps_plan_variant": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_float)]),
     "ps_set_plan_variant": (_c_int, [_c_int, _c_int, _c_int]),
     "ps_set_workspace_budget": (_c_int, [ctypes.c_size_t]),
+    "ps_plan_polychromatic": (_c_int, [_c_int, _c_int, _c_int, _c_int, ctypes.c_size_t, ctypes.POINTER(_c_int),
+                                       ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
     "ps_timing_enable": (_c_int, [_c_int]),
     "ps_timing_count": (_c_int, []),
     "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp,
@@ -183,6 +186,20 @@ def set_workspace_budget(nbytes: int, device=None) -> None:
         raise ValueError("nbytes must be >= 0")
     with torch.cuda.device(torch.device("cuda") if device is None else torch.device(device)):
         _check("ps_set_workspace_budget", load_library().ps_set_workspace_budget(int(nbytes)))
+
+
+def plan_polychromatic(N: int, n_real: int, n_lambda: int, budget_bytes: int, dtype=torch.float32) -> dict:
+    """The split illumination_polychromatic would use for these sizes under
+    the given workspace budget (host arithmetic; no GPU needed)."""
+    if int(budget_bytes) <= 0:
+        raise ValueError("budget_bytes must be > 0")
+    out = [_c_int() for _ in range(4)]
+    ws = ctypes.c_size_t()
+    _check("ps_plan_polychromatic", load_library().ps_plan_polychromatic(
+        int(N), int(n_real), int(n_lambda), _dtype_code(dtype), int(budget_bytes), *[ctypes.byref(o) for o in out],
+        ctypes.byref(ws)))
+    return {"pipelined": bool(out[0].value), "n_jobs": out[1].value, "lambdas_per_job": out[2].value,
+            "real_per_job": out[3].value, "workspace_bytes": ws.value}
 
 
 def timing_enable(on: bool = True) -> None:

@@ -71,6 +71,13 @@ CASES = [(2048, 3, 8, 300 * MiB, 150 * MiB), (2048, 2, 5, 300 * MiB, 150 * MiB),
 
 @pytest.mark.parametrize("N,n_real,n_lambda,bp,bq", CASES)
 def test_pipelined_equals_plain(S, monkeypatch, N, n_real, n_lambda, bp, bq):
+    # the premise: the two budgets give the same split, pipelined and plain
+    monkeypatch.setenv("SCINT_PIPELINE", "1")
+    pl = S.plan_polychromatic(N, n_real, n_lambda, bp)
+    monkeypatch.setenv("SCINT_PIPELINE", "0")
+    ql = S.plan_polychromatic(N, n_real, n_lambda, bq)
+    assert pl["pipelined"] and pl["n_jobs"] >= 2 and not ql["pipelined"]
+    assert (pl["lambdas_per_job"], pl["real_per_job"]) == (ql["lambdas_per_job"], ql["real_per_job"])
     z, lam_ref, lams, w = geometry(N, n_lambda, N + n_lambda)
     if N == 4096:
         S.set_plan_variant(N, 0)  # the 128-thread plan
