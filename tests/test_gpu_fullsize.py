@@ -1,9 +1,11 @@
 """GPU parity at the full sizes of the named workloads, through the same entry
 points and launch configuration that bench.py times.
 
-Where the FP64 oracle finishes in seconds at full size it is compared pixel
-by pixel (4096^2, 10000^2, 16384^2, 2048^2 and 8192^2 single-wavelength
-cases); otherwise properties that hold at any size are checked (mean
+Where the FP64 oracle finishes in seconds to a minute at full size it is
+compared pixel by pixel (4096^2, 10000^2, 16384^2, 2048^2 and 8192^2
+single-wavelength cases, and the bench's own step: realisation 0 of 8 screens
+of 8192^2 over 32 wavelengths and its smears); otherwise properties that hold
+at any size are checked (mean
 intensity 1 by Parseval, the structure function of the screen against its
 exact discrete expectation, the sum over wavelengths equal to the weighted
 single-wavelength patterns, smearing preserving the mean and lowering m).
@@ -149,6 +151,37 @@ def test_poly_8192_batch_properties(S, P):
         acc += S.illumination_polychromatic(phi[0:1], 1.0, c.z, c.lam_ref, [lam]).double() / len(c.lambdas)
     d = (I[0:1].double() - acc).abs().max().item()
     assert d < 2e-6 * acc.max().item()
+
+
+def test_bench_step_realisation0_vs_oracle(S, P, oracle):
+    """The bench's step itself: 8 screens of 8192^2, the propagation over all
+    32 wavelengths pipelined in 8 jobs, 4 disk smears.  Realisation 0 of the
+    batch against the FP64 oracle at every pixel: the co-added pattern and its
+    smears by the smallest and the largest disk."""
+    c = P.POLY_8192
+    N = c.N
+    GiB = 1 << 30
+    S.set_workspace_budget(80 * GiB)
+    try:
+        plan = S.plan_polychromatic(N, c.n_real, len(c.lambdas), 80 * GiB)
+        assert plan["pipelined"] and plan["n_jobs"] == c.n_real
+        phi = S.ps_generate(N, 1.0, c.R_ref, c.beta, c.seed, 0, c.n_real)
+        I = S.illumination_polychromatic(phi, 1.0, c.z, c.lam_ref, c.lambdas)
+        ext = S.source_smear(I, 1.0, c.smear_radii)
+        I0, ext0 = host(I[0]), host(ext[0])
+        del phi, I, ext
+    finally:
+        S.set_workspace_budget(0)
+    phi_ref = oracle.screen(N, c.R_ref, c.beta, c.seed, 0)
+    I_ref = oracle.polychromatic(phi_ref, 1.0, c.z, c.lam_ref, c.lambdas)
+    e_rms, e_max = errs(I0, I_ref)
+    print("bench step, 32 wavelengths: e_rms=%.2e e_max=%.2e" % (e_rms, e_max))
+    assert e_rms < F32_RMS and e_max < F32_MAX
+    for j in (0, len(c.smear_radii) - 1):
+        ref = oracle.smear(I_ref, c.smear_radii[j])
+        e_rms, e_max = errs(ext0[j], ref)
+        print("bench step, disk %.0f px: e_rms=%.2e e_max=%.2e" % (c.smear_radii[j], e_rms, e_max))
+        assert e_rms < F32_RMS and e_max < F32_MAX
 
 
 def test_poly_8192_two_wavelengths_vs_oracle(S, P, oracle):
