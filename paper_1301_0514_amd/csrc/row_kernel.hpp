@@ -680,6 +680,11 @@ using ProgFwdRe = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_STORE_R>;
 using ProgSmearMid = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_SAVE, ROP_LOOP, ROP_RESTORE, ROP_MUL_RTAB2D,
                             ROP_FFT_INV, ROP_STORE_C, ROP_ENDLOOP>;
 using ProgInvRe = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_STORE_R>;
+// the three smear passes carrying transposes of other data (RowSide)
+using ProgRealFwdT = OpList<ROP_SIDE_T, ROP_LOAD_R, ROP_FFT_FWD, ROP_STORE_C>;
+using ProgSmearMidT = OpList<ROP_SIDE_T, ROP_LOAD_C, ROP_FFT_FWD, ROP_SAVE, ROP_LOOP, ROP_RESTORE, ROP_MUL_RTAB2D,
+                             ROP_FFT_INV, ROP_STORE_C, ROP_ENDLOOP>;
+using ProgInvReT = OpList<ROP_SIDE_T, ROP_LOAD_C, ROP_FFT_INV, ROP_STORE_R>;
 using ProgVjpY = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_MUL_RLOAD, ROP_FFT_FWD,
                         ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
 using ProgVjpX = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_GRAD_PHI, ROP_STORE_R,

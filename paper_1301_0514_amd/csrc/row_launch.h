@@ -23,6 +23,9 @@ struct ProgApertureXTag;
 struct ProgAbs2Tag;
 struct ProgPhasePropTTag;     // complex64 only
 struct ProgPropIntensityTTag;  // complex64 only
+struct ProgRealFwdTTag;        // complex64 only
+struct ProgSmearMidTTag;       // complex64 only
+struct ProgInvReTTag;          // complex64 only
 
 // Launches program Tag on total_rows rows of length L (the grid size N) with
 // plan variant V; tw is the device twiddle table of that plan in the same

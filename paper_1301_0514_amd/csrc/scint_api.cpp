@@ -373,6 +373,9 @@ SCINT_PROG_NAME(ProgApertureX)
 SCINT_PROG_NAME(ProgAbs2)
 SCINT_PROG_NAME(ProgPhasePropT)
 SCINT_PROG_NAME(ProgPropIntensityT)
+SCINT_PROG_NAME(ProgRealFwdT)
+SCINT_PROG_NAME(ProgSmearMidT)
+SCINT_PROG_NAME(ProgInvReT)
 #undef SCINT_PROG_NAME
 
 int plan_variant(int N, int dtype, int *V);
@@ -1329,6 +1332,105 @@ static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hi
     return PS_OK;
 }
 
+// ------------------------------------------------------------ source smear
+// One group of the smear: np complex transforms, each holding `step` (2: a
+// pair, 1: a single) realisations; W1/W2 hold np complex grids, V1/V2
+// np n_r.  The three row passes: the forward x pass of the real patterns,
+// the middle pass (y forward, times each disk spectrum, y inverse), and per
+// radius the inverse x pass to real patterns.
+struct SmearJob {
+    const char *Iin;
+    char *Iout;
+    int np, step;
+    char *W1, *W2, *V1, *V2;
+};
+// transposes [u0, u1) of complex64 matrices in -> out, carried by a pass
+struct SmearSide {
+    const void *in;
+    void *out;
+    int64_t u0, u1;
+};
+
+static ProgBuilder smear_rf_prog(int N, const SmearJob &j, size_t rb1, bool side) {
+    const bool pair = j.step == 2;
+    ProgBuilder a(N, (int64_t)j.np * N);
+    if (side) a.op(ROP_SIDE_T);
+    a.op(ROP_LOAD_R, j.Iin, (int64_t)j.step * nn(N), N, 0, pair ? RF_PAIR : 0, 0.0,
+         pair ? const_cast<char *>(j.Iin) + rb1 : nullptr)
+        .op(ROP_FFT_FWD)
+        .op(ROP_STORE_C, j.W1, nn(N), N);
+    return a;
+}
+static ProgBuilder smear_mid_prog(int N, const SmearJob &j, const void *D, int n_r, bool side) {
+    ProgBuilder b(N, (int64_t)j.np * N);
+    b.p.n_iter = n_r;
+    if (side) b.op(ROP_SIDE_T);
+    b.op(ROP_LOAD_C, j.W2, nn(N), N)
+        .op(ROP_FFT_FWD)
+        .op(ROP_SAVE)
+        .op(ROP_LOOP)
+        .op(ROP_RESTORE)
+        .op(ROP_MUL_RTAB2D, D, 0, N, nn(N))
+        .op(ROP_FFT_INV)
+        .op(ROP_STORE_C, j.V1, (int64_t)n_r * nn(N), N, nn(N))
+        .op(ROP_ENDLOOP);
+    return b;
+}
+static ProgBuilder smear_ir_prog(int N, const SmearJob &j, int r, int n_r, size_t rb1, bool side) {
+    const bool pair = j.step == 2;
+    const size_t cbytes = 2 * rb1;
+    ProgBuilder d(N, (int64_t)j.np * N);
+    char *dst = j.Iout + (size_t)r * rb1;
+    if (side) d.op(ROP_SIDE_T);
+    d.op(ROP_LOAD_C, j.V2 + (size_t)r * cbytes, (int64_t)n_r * nn(N), N)
+        .op(ROP_FFT_INV)
+        .op(ROP_STORE_R, dst, (int64_t)j.step * n_r * nn(N), N, 0, pair ? RF_PAIR : 0, 1.0,
+            pair ? dst + (size_t)n_r * rb1 : nullptr);
+    return d;
+}
+static void set_side(RowSide &sd, const SmearSide &t, const SideCfg &sc) {
+    sd.in = t.in;
+    sd.out = t.out;
+    sd.u0 = t.u0;
+    sd.u1 = t.u1;
+    sd.fft_blocks = sc.fft_x;
+    sd.side_blocks = sc.side_x;
+}
+// the passes in any precision, without side transposes
+static int smear_rf_any(int N, int dtype, const SmearJob &j, hipStream_t stream) {
+    ProgBuilder a = smear_rf_prog(N, j, (size_t)nn(N) * real_bytes(dtype), false);
+    return run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream);
+}
+static int smear_mid_any(int N, int dtype, const SmearJob &j, const void *D, int n_r, hipStream_t stream) {
+    ProgBuilder b = smear_mid_prog(N, j, D, n_r, false);
+    return run_row<ProgSmearMidTag>(dtype, N, b.p, b.n, stream);
+}
+static int smear_ir_any(int N, int dtype, const SmearJob &j, int r, int n_r, hipStream_t stream) {
+    ProgBuilder d = smear_ir_prog(N, j, r, n_r, (size_t)nn(N) * real_bytes(dtype), false);
+    return run_row<ProgInvReTag>(dtype, N, d.p, d.n, stream);
+}
+// FP32 passes carrying the transposes `t` (none if NULL)
+static int smear_rf(int N, const SmearJob &j, const SmearSide *t, const SideCfg &sc, hipStream_t stream) {
+    if (!t) return smear_rf_any(N, PS_F32, j, stream);
+    ProgBuilder a = smear_rf_prog(N, j, (size_t)nn(N) * 4, true);
+    set_side(a.p.side, *t, sc);
+    return run_row_side<ProgRealFwdTTag>(N, a.p, a.n, stream);
+}
+static int smear_mid(int N, const SmearJob &j, const void *D, int n_r, const SmearSide *t, const SideCfg &sc,
+                     hipStream_t stream) {
+    if (!t) return smear_mid_any(N, PS_F32, j, D, n_r, stream);
+    ProgBuilder b = smear_mid_prog(N, j, D, n_r, true);
+    set_side(b.p.side, *t, sc);
+    return run_row_side<ProgSmearMidTTag>(N, b.p, b.n, stream);
+}
+static int smear_ir(int N, const SmearJob &j, int r, int n_r, const SmearSide *t, const SideCfg &sc,
+                    hipStream_t stream) {
+    if (!t) return smear_ir_any(N, PS_F32, j, r, n_r, stream);
+    ProgBuilder d = smear_ir_prog(N, j, r, n_r, (size_t)nn(N) * 4, true);
+    set_side(d.p.side, *t, sc);
+    return run_row_side<ProgInvReTTag>(N, d.p, d.n, stream);
+}
+
 int source_smear(int N, double delta, const void *I_in, const double *radii, int n_r, int n_real, int dtype,
                  void *I_out, void *hip_stream) {
     g_last_error.clear();
@@ -1364,41 +1466,43 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
         char *W2 = base + c.take(cbytes * nb);
         char *V1 = base + c.take(cbytes * nb * n_r);
         char *V2 = base + c.take(cbytes * nb * n_r);
+        const SideCfg sc = side_cfg();
         for (int pb = 0; pb < nb;) {
             const bool pair = nb - pb >= 2;
             const int np = pair ? (nb - pb) / 2 : 1;  // complex transforms in this group
             const int step = pair ? 2 : 1;            // realisations per transform
             const char *Iin = static_cast<const char *>(I_in) + (size_t)(b0 + pb) * rb1;
-            ProgBuilder a(N, (int64_t)np * N);
-            a.op(ROP_LOAD_R, Iin, (int64_t)step * nn(N), N, 0, pair ? RF_PAIR : 0, 0.0,
-                 pair ? const_cast<char *>(Iin) + rb1 : nullptr)
-                .op(ROP_FFT_FWD)
-                .op(ROP_STORE_C, W1, nn(N), N);
-            if (int rc = run_row<ProgRealFwdTag>(dtype, N, a.p, a.n, stream)) return rc;
-            if (int rc = transpose(W1, W2, N, np, (int)(cbytes / nn(N)), stream)) return rc;
-            ProgBuilder b(N, (int64_t)np * N);
-            b.p.n_iter = n_r;
-            b.op(ROP_LOAD_C, W2, nn(N), N)
-                .op(ROP_FFT_FWD)
-                .op(ROP_SAVE)
-                .op(ROP_LOOP)
-                .op(ROP_RESTORE)
-                .op(ROP_MUL_RTAB2D, D, 0, N, nn(N))
-                .op(ROP_FFT_INV)
-                .op(ROP_STORE_C, V1, (int64_t)n_r * nn(N), N, nn(N))
-                .op(ROP_ENDLOOP);
-            if (int rc = run_row<ProgSmearMidTag>(dtype, N, b.p, b.n, stream)) return rc;
-            if (int rc = transpose(V1, V2, N, (int64_t)np * n_r, (int)(cbytes / nn(N)), stream)) return rc;
             // I_out[b][r]: transform q holds realisations b0 + pb + step q (and + 1)
             char *Iout = static_cast<char *>(I_out) + (size_t)(b0 + pb) * n_r * rb1;
-            for (int r = 0; r < n_r; ++r) {
-                ProgBuilder d(N, (int64_t)np * N);
-                char *dst = Iout + (size_t)r * rb1;
-                d.op(ROP_LOAD_C, V2 + (size_t)r * cbytes, (int64_t)n_r * nn(N), N)
-                    .op(ROP_FFT_INV)
-                    .op(ROP_STORE_R, dst, (int64_t)step * n_r * nn(N), N, 0, pair ? RF_PAIR : 0, 1.0,
-                        pair ? dst + (size_t)n_r * rb1 : nullptr);
-                if (int rc = run_row<ProgInvReTag>(dtype, N, d.p, d.n, stream)) return rc;
+            SmearJob all{Iin, Iout, np, step, W1, W2, V1, V2};
+            if (dtype == PS_F32 && N >= 2048 && np >= 2 && sc.on) {
+                // two jobs, the transposes of each riding on the other's passes
+                const int q0 = (np + 1) / 2;
+                const SmearJob j0{Iin, Iout, q0, step, W1, W2, V1, V2};
+                const size_t o = (size_t)q0 * cbytes;  // offset of job 1 in the complex buffers
+                const SmearJob j1{Iin + (size_t)q0 * step * rb1, Iout + (size_t)q0 * step * n_r * rb1, np - q0, step,
+                                  W1 + o, W2 + o, V1 + o * n_r, V2 + o * n_r};
+                const int64_t upm = (int64_t)transpose_units_x(N) * transpose_units_y(N);
+                const SmearSide t1_0{j0.W1, j0.W2, 0, upm * j0.np}, t1_1{j1.W1, j1.W2, 0, upm * j1.np};
+                const SmearSide t2_0{j0.V1, j0.V2, 0, upm * j0.np * n_r};
+                const int64_t U2 = upm * j1.np * n_r;
+                if (int rc = smear_rf(N, j0, nullptr, sc, stream)) return rc;
+                if (int rc = smear_rf(N, j1, &t1_0, sc, stream)) return rc;
+                if (int rc = smear_mid(N, j0, D, n_r, &t1_1, sc, stream)) return rc;
+                if (int rc = smear_mid(N, j1, D, n_r, &t2_0, sc, stream)) return rc;
+                for (int r = 0; r < n_r; ++r) {
+                    const SmearSide t2_1{j1.V1, j1.V2, U2 * r / n_r, U2 * (r + 1) / n_r};
+                    if (int rc = smear_ir(N, j0, r, n_r, t2_1.u1 > t2_1.u0 ? &t2_1 : nullptr, sc, stream)) return rc;
+                }
+                for (int r = 0; r < n_r; ++r)
+                    if (int rc = smear_ir(N, j1, r, n_r, nullptr, sc, stream)) return rc;
+            } else {
+                if (int rc = smear_rf_any(N, dtype, all, stream)) return rc;
+                if (int rc = transpose(W1, W2, N, np, (int)(cbytes / nn(N)), stream)) return rc;
+                if (int rc = smear_mid_any(N, dtype, all, D, n_r, stream)) return rc;
+                if (int rc = transpose(V1, V2, N, (int64_t)np * n_r, (int)(cbytes / nn(N)), stream)) return rc;
+                for (int r = 0; r < n_r; ++r)
+                    if (int rc = smear_ir_any(N, dtype, all, r, n_r, stream)) return rc;
             }
             pb += np * step;
         }

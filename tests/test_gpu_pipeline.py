@@ -249,3 +249,36 @@ def test_pipelined_equals_plain_large_workgroups(S, monkeypatch, N):
     b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, False)
     assert torch.equal(a, b)
     assert float(a.mean()) == pytest.approx(1.0, abs=1e-5)
+
+
+# ------------------------------------------------------------------ smear
+# source_smear from N = 2048 up (FP32) with two or more realisation pairs runs
+# its pairs as two jobs, each job's transposes carried by the other's passes;
+# every pair's arithmetic is unchanged, so the result is the plain path's bit
+# for bit.
+@pytest.mark.parametrize("N,n_real,radii", [(2048, 4, [3.0]), (2048, 5, [2.0, 9.0, 30.0]),
+                                            (2048, 8, [5.0, 20.0, 40.0, 80.0]), (4000, 4, [6.0, 25.0]),
+                                            (10000, 4, [12.0])])
+def test_smear_pipelined_equals_plain(S, monkeypatch, N, n_real, radii):
+    g = torch.Generator(device="cuda").manual_seed(N + n_real)
+    I = torch.rand((n_real, N, N), generator=g, device="cuda") + 0.5
+    monkeypatch.setenv("SCINT_PIPELINE", "1")
+    a = S.source_smear(I, 1.0, radii)
+    monkeypatch.setenv("SCINT_PIPELINE", "0")
+    b = S.source_smear(I, 1.0, radii)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_smear_pipelined_vs_oracle(S, oracle):
+    import inputs
+    N, radii = 2048, [4.0, 33.0]
+    I = inputs.intensity_field(N, seed=21, n=4)
+    out = S.source_smear(torch.tensor(I.astype(np.float32), device="cuda"), 1.0, radii)
+    out = out.double().cpu().numpy()
+    for b in (0, 3):
+        for j, R in enumerate(radii):
+            ref = oracle.smear(I[b].astype(np.float32).astype(np.float64), R)
+            m = ref.mean()
+            d = out[b, j] - ref
+            assert np.sqrt(np.mean(d * d)) / m < F32_RMS and np.abs(d).max() / m < F32_MAX
