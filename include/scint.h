@@ -92,6 +92,10 @@ int ps_supported_size_at(int dtype, int i);
  *   phi_out           device [n_real][N][N] real (dtype)
  * A warning (ps_last_warning) is set when delta >= r_diff/2, the sampling
  * criterion of Sect. 3.2.2.
+ * In FP32 from N = 2048 a batch is split into up to four jobs of consecutive
+ * realisations whose noise passes carry the previous job's transpose as
+ * extra workgroups (SCINT_SCREEN_JOBS=<n> in the environment sets the
+ * number, 1 turns the split off); every value is the same bit for bit.
  */
 int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed,
                 uint32_t first_realisation, int n_real, int dtype, void *phi_out,

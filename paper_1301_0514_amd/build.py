@@ -27,7 +27,7 @@ PROGRAMS = ["ProgNoise", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgP
             "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX",
             "ProgApertureX", "ProgAbs2"]
 # programs built for float only (their side transposes are complex64)
-PROGRAMS_F32 = ["ProgPhasePropT", "ProgPropIntensityT", "ProgRealFwdT", "ProgSmearMidT", "ProgInvReT"]
+PROGRAMS_F32 = ["ProgNoiseT", "ProgPhasePropT", "ProgPropIntensityT", "ProgRealFwdT", "ProgSmearMidT", "ProgInvReT"]
 
 # gfx950 only; packed FP32 instructions are disabled (the compiler would
 # otherwise form them from float code).

@@ -224,9 +224,10 @@ struct U32x4 {
 __device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x0), lo0 = 0xD2511F53u * c.x0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.x2), lo1 = 0xCD9E8D57u * c.x2;
-        c = U32x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
+        // each 32 x 32 -> 64-bit product as one full-width multiply (one
+        // v_mad_u64_u32) rather than separate high and low halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x0, p1 = (uint64_t)0xCD9E8D57u * c.x2;
+        c = U32x4{(uint32_t)(p1 >> 32) ^ c.x1 ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.x3 ^ k1, (uint32_t)p0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -661,6 +661,8 @@ __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_
 // The row programs used by the library.  Each name lists its op codes; the
 // host fills the operands of op[i] for code i.
 using ProgNoise = OpList<ROP_NOISE, ROP_FFT_INV, ROP_STORE_C>;
+// the noise pass carrying the transpose of an earlier batch's output (RowSide)
+using ProgNoiseT = OpList<ROP_SIDE_T, ROP_NOISE, ROP_FFT_INV, ROP_STORE_C>;
 using ProgScreen = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R>;
 using ProgScreenProp = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R, ROP_EXP_RE, ROP_FFT_FWD,
                               ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;

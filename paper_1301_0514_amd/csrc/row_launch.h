@@ -21,6 +21,7 @@ struct ProgVjpYTag;
 struct ProgVjpXTag;
 struct ProgApertureXTag;
 struct ProgAbs2Tag;
+struct ProgNoiseTTag;          // complex64 only
 struct ProgPhasePropTTag;     // complex64 only
 struct ProgPropIntensityTTag;  // complex64 only
 struct ProgRealFwdTTag;        // complex64 only

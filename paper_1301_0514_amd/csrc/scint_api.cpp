@@ -371,6 +371,7 @@ SCINT_PROG_NAME(ProgVjpY)
 SCINT_PROG_NAME(ProgVjpX)
 SCINT_PROG_NAME(ProgApertureX)
 SCINT_PROG_NAME(ProgAbs2)
+SCINT_PROG_NAME(ProgNoiseT)
 SCINT_PROG_NAME(ProgPhasePropT)
 SCINT_PROG_NAME(ProgPropIntensityT)
 SCINT_PROG_NAME(ProgRealFwdT)
@@ -592,15 +593,87 @@ size_t workspace_budget() {
 }
 
 // ------------------------------------------------------------ pipelines
-// Screen of nb realisations into phi (and optionally through the
-// propagation into I).  W1/W2: complex [nb][N][N] workspaces.
+// Interleaving of the pipelined propagation below: the share of each job's
+// transpose units carried by the next job's x pass (the rest rides on the y
+// pass two jobs back), and per pass the row workgroups and transpose
+// workgroups of one group of the grid.  Measured at 8192^2 x 32 wavelengths
+// on the MI355X (step times within 1 %: shares of 0.5 to 1 on the x pass;
+// groups of 16 + 4, 32 + 8 or 64 + 16 row + transpose workgroups, i.e. 128
+// units per transpose workgroup; 12-16 % slower: 1 : 1 and 3 : 1 groups):
+// the x pass takes all of a job's transposes (the y pass only the last
+// job's), in groups of 32 + 8.  SCINT_PIPELINE=0 in the environment turns
+// the pipeline off; SCINT_SIDE_SPLIT=<f> and SCINT_SIDE_GROUPS=
+// <rows_x>:<side_x>:<rows_y>:<side_y> override the defaults.  The screen
+// passes split a batch into up to screen_jobs jobs (SCINT_SCREEN_JOBS=<n>;
+// 1 turns that pipeline off).
+struct SideCfg {
+    bool on = true;
+    double split = 1.0;
+    int fft_x = 32, side_x = 8, fft_y = 32, side_y = 8;
+    int screen_jobs = 4;
+};
+static SideCfg side_cfg() {
+    SideCfg c;
+    if (const char *e = std::getenv("SCINT_PIPELINE")) c.on = std::atoi(e) != 0;
+    if (const char *e = std::getenv("SCINT_SIDE_SPLIT")) {
+        const double v = std::atof(e);
+        if (v >= 0.0 && v <= 1.0) c.split = v;
+    }
+    if (const char *e = std::getenv("SCINT_SCREEN_JOBS")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 64) c.screen_jobs = v;
+    }
+    if (const char *e = std::getenv("SCINT_SIDE_GROUPS")) {
+        int a = 0, b = 0, d = 0, f = 0;
+        if (std::sscanf(e, "%d:%d:%d:%d", &a, &b, &d, &f) == 4 && a >= 1 && b >= 1 && d >= 1 && f >= 1 &&
+            a <= 1024 && b <= 1024 && d <= 1024 && f <= 1024) {
+            c.fft_x = a;
+            c.side_x = b;
+            c.fft_y = d;
+            c.side_y = f;
+        }
+    }
+    return c;
+}
+
+// The first pass of the screens of nb realisations (noise, spectral filter,
+// inverse DFT along rows) into W1 and its transpose into W2, both complex
+// [nb][N][N].  In FP32 from N = 2048 the batch is split into up to
+// screen_jobs jobs of consecutive realisations: the noise pass of job k
+// carries the transpose of job k-1 as extra workgroups (its arithmetic-bound
+// FFTs leave memory bandwidth free), and only the last job's transpose runs
+// on its own.  Each element is computed by the same kernel code either way,
+// so the results do not depend on the split.
 int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int nb, int dtype, void *W1, void *W2,
                   hipStream_t stream) {
-    ProgBuilder a(N, (int64_t)nb * N);
-    set_noise(a.p, N, R, beta, seed, r0);
-    a.op(ROP_NOISE).op(ROP_FFT_INV).op(ROP_STORE_C, W1, nn(N), N);
-    if (int rc = run_row<ProgNoiseTag>(dtype, N, a.p, a.n, stream)) return rc;
-    return transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream);
+    const SideCfg sc = side_cfg();
+    const int J = (dtype == PS_F32 && N >= 2048 && sc.on) ? std::min(nb, sc.screen_jobs) : 1;
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const int64_t upm = (int64_t)transpose_units_x(N) * transpose_units_y(N);
+    int prev0 = 0, prev_n = 0;  // realisations of the previous job
+    for (int k = 0; k < J; ++k) {
+        const int j0 = (int)((int64_t)nb * k / J), jn = (int)((int64_t)nb * (k + 1) / J) - j0;
+        ProgBuilder a(N, (int64_t)jn * N);
+        set_noise(a.p, N, R, beta, seed, r0 + (uint32_t)j0);
+        if (k > 0) a.op(ROP_SIDE_T);
+        a.op(ROP_NOISE).op(ROP_FFT_INV).op(ROP_STORE_C, static_cast<char *>(W1) + j0 * cbytes, nn(N), N);
+        if (k == 0) {
+            if (int rc = run_row<ProgNoiseTag>(dtype, N, a.p, a.n, stream)) return rc;
+        } else {
+            RowSide &sd = a.p.side;
+            sd.in = static_cast<char *>(W1) + prev0 * cbytes;
+            sd.out = static_cast<char *>(W2) + prev0 * cbytes;
+            sd.u0 = 0;
+            sd.u1 = upm * prev_n;
+            sd.fft_blocks = sc.fft_x;
+            sd.side_blocks = sc.side_x;
+            if (int rc = run_row_side<ProgNoiseTTag>(N, a.p, a.n, stream)) return rc;
+        }
+        prev0 = j0;
+        prev_n = jn;
+    }
+    return transpose(static_cast<char *>(W1) + prev0 * cbytes, static_cast<char *>(W2) + prev0 * cbytes, N, prev_n,
+                     2 * (int)real_bytes(dtype), stream);
 }
 
 }  // namespace
@@ -854,42 +927,6 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
         .op(ROP_ENDLOOP)
         .op(ROP_STORE_ACC, Iacc, nn(N), N, 0, add ? RF_ADD : 0);
     return run_row<ProgPropIntensityTag>(dtype, N, b.p, b.n, stream);
-}
-
-// Interleaving of the pipelined propagation below: the share of each job's
-// transpose units carried by the next job's x pass (the rest rides on the y
-// pass two jobs back), and per pass the row workgroups and transpose
-// workgroups of one group of the grid.  Measured at 8192^2 x 32 wavelengths
-// on the MI355X (step times within 1 %: shares of 0.5 to 1 on the x pass;
-// groups of 16 + 4, 32 + 8 or 64 + 16 row + transpose workgroups, i.e. 128
-// units per transpose workgroup; 12-16 % slower: 1 : 1 and 3 : 1 groups):
-// the x pass takes all of a job's transposes (the y pass only the last
-// job's), in groups of 32 + 8.  SCINT_PIPELINE=0 in the environment turns
-// the pipeline off; SCINT_SIDE_SPLIT=<f> and SCINT_SIDE_GROUPS=
-// <rows_x>:<side_x>:<rows_y>:<side_y> override the defaults.
-struct SideCfg {
-    bool on = true;
-    double split = 1.0;
-    int fft_x = 32, side_x = 8, fft_y = 32, side_y = 8;
-};
-static SideCfg side_cfg() {
-    SideCfg c;
-    if (const char *e = std::getenv("SCINT_PIPELINE")) c.on = std::atoi(e) != 0;
-    if (const char *e = std::getenv("SCINT_SIDE_SPLIT")) {
-        const double v = std::atof(e);
-        if (v >= 0.0 && v <= 1.0) c.split = v;
-    }
-    if (const char *e = std::getenv("SCINT_SIDE_GROUPS")) {
-        int a = 0, b = 0, d = 0, f = 0;
-        if (std::sscanf(e, "%d:%d:%d:%d", &a, &b, &d, &f) == 4 && a >= 1 && b >= 1 && d >= 1 && f >= 1 &&
-            a <= 1024 && b <= 1024 && d <= 1024 && f <= 1024) {
-            c.fft_x = a;
-            c.side_x = b;
-            c.fft_y = d;
-            c.side_y = f;
-        }
-    }
-    return c;
 }
 
 // One job of the polychromatic propagation: nb realisations from b0, m

@@ -12,7 +12,9 @@ Cases: many jobs of two wavelengths; a ragged last wavelength chunk; ragged
 transpose units (N = 4000 is not a multiple of 128 or 64) with 200-thread
 row workgroups, and 128-thread ones (4096, plan 0), where threads take two
 lane roles of the transpose; the bench's shape (8192, 32 wavelengths, two realisations: two
-jobs); the pipeline's prologue and epilogue with two and three jobs.
+jobs); the pipeline's prologue and epilogue with two and three jobs.  The
+sections at the end check the same property for the source smear and the
+screens, whose passes carry each other's transposes in the same way.
 """
 import numpy as np
 import pytest
@@ -282,3 +284,35 @@ def test_smear_pipelined_vs_oracle(S, oracle):
             m = ref.mean()
             d = out[b, j] - ref
             assert np.sqrt(np.mean(d * d)) / m < F32_RMS and np.abs(d).max() / m < F32_MAX
+
+
+# ------------------------------------------------------------------ screens
+# ps_generate from N = 2048 up (FP32) splits a batch of realisations into up
+# to four jobs; the noise pass of each job carries the transpose of the
+# previous job's output and only the last job's transpose runs on its own.
+# Every element is computed by the same code, so the screens equal the
+# one-job path's bit for bit (SCINT_SCREEN_JOBS=1).
+@pytest.mark.parametrize("N,n_real,jobs", [(2048, 8, "4"), (2048, 3, "4"), (2048, 5, "2"), (4000, 5, "4"),
+                                           (10000, 2, "4")])
+def test_screen_pipelined_equals_plain(S, monkeypatch, N, n_real, jobs):
+    monkeypatch.setenv("SCINT_SCREEN_JOBS", jobs)
+    a = S.ps_generate(N, 1.0, N / 100.0, 11 / 3, 5, 7, n_real)
+    monkeypatch.setenv("SCINT_SCREEN_JOBS", "1")
+    b = S.ps_generate(N, 1.0, N / 100.0, 11 / 3, 5, 7, n_real)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_screen_pipelined_vs_oracle(S, oracle, monkeypatch):
+    # eight realisations in four jobs: realisation 1 is transposed on the
+    # second job's noise pass, realisation 7 by the last, standalone transpose
+    monkeypatch.delenv("SCINT_SCREEN_JOBS", raising=False)
+    N, R, seed, r0 = 2048, 24.0, 29, 40
+    phi = S.ps_generate(N, 1.0, R, 11 / 3, seed, r0, 8).double().cpu().numpy()
+    for b in (1, 7):
+        ref = oracle.screen(N, R, 11 / 3, seed, r0 + b)
+        d = phi[b] - ref
+        scale = np.sqrt(np.mean(ref * ref))
+        # the FP32 screen bar of the parity tests: RMS 3e-6, max 30 x that
+        assert np.sqrt(np.mean(d * d)) < 3e-6 * scale
+        assert np.abs(d).max() < 9e-5 * np.abs(ref).max()
