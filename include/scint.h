@@ -149,7 +149,9 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
  * two 1-D passes of one job runs inside the launches of the neighbouring
  * jobs' passes, which takes twice the workspace of the plain loop and gives
  * the same result bit for bit for the same job split (environment
- * SCINT_PIPELINE=0 turns it off).
+ * SCINT_PIPELINE=0 turns it off).  The pipelined first passes give each row
+ * two workgroups, each taking half of the job's wavelengths (same result;
+ * SCINT_ITER_SPLIT=1 keeps one).
  */
 int illumination_polychromatic(int N, double delta, double z, const void *phi_ref,
                                double lambda_ref, const double *lambdas,

@@ -19,11 +19,16 @@ namespace scint {
 template <int L, int V>
 static hipError_t launch_one(const RowProgram &prog, const void *tw, hipStream_t stream) {
     using Cfg = RowCfg<SCINT_REAL, L, V>;
-    const int rows_blocks = (prog.total_rows + Cfg::B - 1) / Cfg::B;
+    RowProgram p = prog;
+    // two workgroups per row only where the program allows it, the loop has
+    // two or more iterations and the row workgroups come in whole eights
+    const int row_wgs = (prog.total_rows + Cfg::B - 1) / Cfg::B;
+    p.iter_split = (prog.iter_split == 2 && iter_splittable<SCINT_PROG>() && prog.n_iter >= 2 && row_wgs % 8 == 0)
+                       ? 2 : 1;
+    const int rows_blocks = row_wgs * p.iter_split;
     if constexpr (has_side<SCINT_PROG>()) {
         // groups of fft_blocks row workgroups and side_blocks transpose
         // workgroups; the units are spread evenly over the latter
-        RowProgram p = prog;
         RowSide &sd = p.side;
         const int64_t units = sd.u1 - sd.u0;
         if (sd.fft_blocks < 1 || sd.side_blocks < 1 || units < 1 || sd.u0 < 0 || !sd.in || !sd.out)
@@ -39,7 +44,7 @@ static hipError_t launch_one(const RowProgram &prog, const void *tw, hipStream_t
                            static_cast<const cpx<SCINT_REAL> *>(tw));
     } else {
         hipLaunchKernelGGL((row_kernel<SCINT_REAL, L, V, SCINT_PROG>), dim3(rows_blocks), dim3(Cfg::THREADS), 0,
-                           stream, prog, static_cast<const cpx<SCINT_REAL> *>(tw));
+                           stream, p, static_cast<const cpx<SCINT_REAL> *>(tw));
     }
     return hipGetLastError();
 }

@@ -392,7 +392,7 @@ template <typename Real, int L, int V> struct RowState {
     const cpx<Real> *tw;
     const cpx<Real> *twc;  // twiddle cache in LDS (or NULL)
     double *red;
-    int t, tid, g, batch, row, it;
+    int t, tid, g, batch, row, it, it0, it1;  // it0, it1: this workgroup's range of loop iterations
     bool valid;
 };
 
@@ -565,7 +565,7 @@ __device__ __forceinline__ void run_ops(RowState<Real, L, V> &st) {
         if constexpr (c == ROP_LOOP) {
             constexpr int e = find_endloop<Ops>(I);
 #pragma clang loop unroll(disable)
-            for (st.it = 0; st.it < st.prog->n_iter; ++st.it) run_ops<Real, L, V, Ops, I + 1, e>(st);
+            for (st.it = st.it0; st.it < st.it1; ++st.it) run_ops<Real, L, V, Ops, I + 1, e>(st);
             st.it = 0;
             run_ops<Real, L, V, Ops, e + 1, End>(st);
         } else {
@@ -576,6 +576,21 @@ __device__ __forceinline__ void run_ops(RowState<Real, L, V> &st) {
 }
 
 template <class Ops> constexpr bool has_side() { return Ops::n > 0 && Ops::code[0] == ROP_SIDE_T; }
+
+// Whether a program's loop iterations may be split between two workgroups
+// (RowProgram::iter_split): one loop, nothing after it, and inside it only
+// per-iteration loads, transforms, table products and stores.
+template <class Ops> constexpr bool iter_splittable() {
+    int i = has_side<Ops>() ? 1 : 0;
+    if (i >= Ops::n || Ops::code[i] != ROP_LOOP) return false;
+    for (++i; i < Ops::n && Ops::code[i] != ROP_ENDLOOP; ++i) {
+        const int c = Ops::code[i];
+        if (c != ROP_LOAD_PHASE && c != ROP_LOAD_C && c != ROP_FFT_FWD && c != ROP_FFT_INV && c != ROP_MUL_TAB &&
+            c != ROP_STORE_C)
+            return false;
+    }
+    return i == Ops::n - 1;
+}
 
 // LDS of a row kernel: the row pass's, or the transpose tile's if larger
 // (programs with side transposes)
@@ -628,6 +643,20 @@ __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_
             return;
         }
         rb = grp * sd.fft_blocks + r;
+    }
+    int it0 = 0, it1 = prog.n_iter;
+    if constexpr (iter_splittable<Ops>()) {
+        if (prog.iter_split == 2) {
+            // row workgroups q and q + 8 of each 16 share row workgroup
+            // 8 (q / 16) + q % 8
+            const int half = (rb >> 3) & 1;
+            rb = ((rb >> 4) << 3) | (rb & 7);
+            const int h = (prog.n_iter + 1) / 2;
+            it0 = half ? h : 0;
+            it1 = half ? prog.n_iter : h;
+        }
+    }
+    if constexpr (has_side<Ops>()) {
         if ((int64_t)rb * B >= prog.total_rows) return;
     }
     RowState<Real, L, V> st;
@@ -650,6 +679,8 @@ __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_
         st.twc = twc;
     }
     st.it = 0;
+    st.it0 = it0;
+    st.it1 = it1;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         st.v[m] = {(Real)0, (Real)0};

@@ -99,6 +99,14 @@ struct RowProgram {
     double neg_beta_4;   // -beta/4                                 (ROP_NOISE)
     double scale[kRowMaxIter];
     double weight[kRowMaxIter];
+    // 1, or 2: each row is taken by two workgroups, 8 apart in launch order
+    // (one XCD, dispatched together), the first doing the loop's first
+    // ceil(n_iter/2) iterations and the second the rest, so that per-row
+    // operands re-read in every iteration are fetched by both from one L2.
+    // Only for programs whose iterations are independent; the launcher
+    // falls back to 1 where it does not apply (the results are the same).
+    int32_t iter_split;
+    int32_t reserved;
 };
 
 // Feature sets: which register arrays beyond the row itself a kernel keeps.

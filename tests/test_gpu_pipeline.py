@@ -316,3 +316,23 @@ def test_screen_pipelined_vs_oracle(S, oracle, monkeypatch):
         # the FP32 screen bar of the parity tests: RMS 3e-6, max 30 x that
         assert np.sqrt(np.mean(d * d)) < 3e-6 * scale
         assert np.abs(d).max() < 9e-5 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ x-pass split
+# The pipelined x passes give each row two workgroups, each taking half of
+# the job's wavelengths; the launcher keeps one where the row workgroups do
+# not come in whole eights or a job has a single wavelength.  Every element
+# is computed by the same code either way, so the result is unchanged bit
+# for bit (SCINT_ITER_SPLIT=1 keeps one workgroup per row).
+@pytest.mark.parametrize("N,n_real,n_lambda", [(2048, 2, 5), (2560, 2, 4), (4000, 1, 3), (8192, 1, 3)])
+def test_x_pass_split_equals_unsplit(S, monkeypatch, N, n_real, n_lambda):
+    z, lam_ref, lams, w = geometry(N, n_lambda, N)
+    phi = S.ps_generate(N, 1.0, N / 100.0, 11 / 3, 3, 0, n_real)
+    monkeypatch.setenv("SCINT_PIPELINE", "1")
+    monkeypatch.setenv("SCINT_ITER_SPLIT", "2")
+    a = S.illumination_polychromatic(phi, 1.0, z, lam_ref, lams, w)
+    monkeypatch.setenv("SCINT_ITER_SPLIT", "1")
+    b = S.illumination_polychromatic(phi, 1.0, z, lam_ref, lams, w)
+    torch.cuda.synchronize()
+    assert S.plan_polychromatic(N, n_real, n_lambda, 96 << 30)["pipelined"]
+    assert torch.equal(a, b)
