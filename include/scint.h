@@ -54,7 +54,7 @@ typedef enum {
     PS_E_ALLOC = -5,         /* device memory for the workspace or cache failed */
     PS_E_DEVICE = -6,        /* a HIP call or kernel launch failed              */
     PS_E_ALIAS = -7,         /* output overlaps an input where that is not allowed */
-    PS_E_UNIMPLEMENTED = -8  /* combination not provided by this build          */
+    PS_E_UNIMPLEMENTED = -8  /* combination the library does not provide       */
 } ps_status;
 
 /* 1 if N is supported for dtype, else 0.  The FP32 set is
