@@ -293,7 +293,7 @@ def test_smear_pipelined_vs_oracle(S, oracle):
 # Every element is computed by the same code, so the screens equal the
 # one-job path's bit for bit (SCINT_SCREEN_JOBS=1).
 @pytest.mark.parametrize("N,n_real,jobs", [(2048, 8, "4"), (2048, 3, "4"), (2048, 5, "2"), (4000, 5, "4"),
-                                           (10000, 2, "4")])
+                                           (10000, 2, "4"), (20000, 2, "4")])
 def test_screen_pipelined_equals_plain(S, monkeypatch, N, n_real, jobs):
     monkeypatch.setenv("SCINT_SCREEN_JOBS", jobs)
     a = S.ps_generate(N, 1.0, N / 100.0, 11 / 3, 5, 7, n_real)
@@ -336,3 +336,17 @@ def test_x_pass_split_equals_unsplit(S, monkeypatch, N, n_real, n_lambda):
     torch.cuda.synchronize()
     assert S.plan_polychromatic(N, n_real, n_lambda, 96 << 30)["pipelined"]
     assert torch.equal(a, b)
+
+
+def test_screen_fresnel_pipelined_equals_plain(S, monkeypatch):
+    # ps_screen_fresnel shares the screens' first pass and its job split
+    N, n_real = 2048, 3
+    rho = N / 12.0
+    lam = 650e-9
+    z = 2 * np.pi * rho ** 2 / lam
+    monkeypatch.setenv("SCINT_SCREEN_JOBS", "4")
+    Ia, pa = S.ps_screen_fresnel(N, 1.0, 20.0, 11 / 3, 9, lam, z, first_realisation=2, n_real=n_real, want_phi=True)
+    monkeypatch.setenv("SCINT_SCREEN_JOBS", "1")
+    Ib, pb = S.ps_screen_fresnel(N, 1.0, 20.0, 11 / 3, 9, lam, z, first_realisation=2, n_real=n_real, want_phi=True)
+    torch.cuda.synchronize()
+    assert torch.equal(pa, pb) and torch.equal(Ia, Ib)
