@@ -11,11 +11,12 @@ namespace scint {
 hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes,
                             hipStream_t stream);
 
-// tab[j][k] = scale * exp(-2 pi i a[j] k'^2), k' the signed frequency of k,
-// for j < n (n <= 64); a[j] = pi rho_j^2 / N^2 (turns per k'^2).  The turn
-// count is formed and reduced in FP64 and the sine/cosine taken in FP64.
+// tab[j][k] = scale amp[j] exp(-2 pi i a[j] k'^2), k' the signed frequency
+// of k, for j < n (n <= 64); a[j] = pi rho_j^2 / N^2 (turns per k'^2); amp
+// NULL means amp[j] = 1.  The turn count is formed and reduced in FP64 and
+// the sine/cosine taken in FP64.
 hipError_t launch_chirp_tables(void *tab, int N, const double *a, int n, double scale, bool f64,
-                               hipStream_t stream);
+                               hipStream_t stream, const double *amp = nullptr);
 
 // img[y][x] = value if dx^2 + dy^2 <= r2 (minimum-image offsets of pixel
 // (x, y) from the origin), else 0.

@@ -82,6 +82,7 @@ hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, in
 // ---------------------------------------------------------------- chirp
 struct ChirpArgs {
     double a[64];
+    double amp[64];
 };
 
 template <typename Real>
@@ -94,14 +95,18 @@ __global__ __launch_bounds__(256) void chirp_kernel(cpx<Real> *tab, int N, Chirp
     const double f = turns - rint(turns);
     double s, c;
     sincospi(2.0 * f, &s, &c);
-    tab[(int64_t)j * N + k] = {(Real)(scale * c), (Real)(-scale * s)};
+    const double g = scale * args.amp[j];
+    tab[(int64_t)j * N + k] = {(Real)(g * c), (Real)(-g * s)};
 }
 
 hipError_t launch_chirp_tables(void *tab, int N, const double *a, int n, double scale, bool f64,
-                               hipStream_t stream) {
+                               hipStream_t stream, const double *amp) {
     if (n < 1 || n > 64) return hipErrorInvalidValue;
     ChirpArgs args{};
-    for (int j = 0; j < n; ++j) args.a[j] = a[j];
+    for (int j = 0; j < n; ++j) {
+        args.a[j] = a[j];
+        args.amp[j] = amp ? amp[j] : 1.0;
+    }
     dim3 grid((N + 255) / 256, n);
     if (f64)
         hipLaunchKernelGGL((chirp_kernel<double>), grid, dim3(256), 0, stream, static_cast<cpx<double> *>(tab), N,

@@ -508,6 +508,9 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         const Real w = (Real)((op.flags & RF_ITER_WEIGHT) ? st.prog->weight[st.it] : op.param);
 #pragma unroll
         for (int m = 0; m < E; ++m) st.acc[m] += w * (v[m].re * v[m].re + v[m].im * v[m].im);
+    } else if constexpr (CODE == ROP_ACC_ABS2U) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) st.acc[m] = fma(v[m].im, v[m].im, fma(v[m].re, v[m].re, st.acc[m]));
     } else if constexpr (CODE == ROP_STORE_ACC) {
         if (valid) {
             Real *dst = static_cast<Real *>(const_cast<void *>(op.ptr)) + off;
@@ -701,13 +704,15 @@ using ProgScreenProp = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R,
 // costs more in occupancy than the cached re-read)
 using ProgPhaseProp = OpList<ROP_LOOP, ROP_LOAD_PHASE, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C,
                              ROP_ENDLOOP>;
-using ProgPropIntensity = OpList<ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_ACC_ABS2,
+// (the weights of a co-addition ride in the chirp tables, so the sum of
+// |.|^2 takes no product by them)
+using ProgPropIntensity = OpList<ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_ACC_ABS2U,
                                  ROP_ENDLOOP, ROP_STORE_ACC>;
 // the two propagation passes carrying transposes of other data (RowSide)
 using ProgPhasePropT = OpList<ROP_SIDE_T, ROP_LOOP, ROP_LOAD_PHASE, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV,
                               ROP_STORE_C, ROP_ENDLOOP>;
 using ProgPropIntensityT = OpList<ROP_SIDE_T, ROP_LOOP, ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV,
-                                  ROP_ACC_ABS2, ROP_ENDLOOP, ROP_STORE_ACC>;
+                                  ROP_ACC_ABS2U, ROP_ENDLOOP, ROP_STORE_ACC>;
 using ProgRealFwd = OpList<ROP_LOAD_R, ROP_FFT_FWD, ROP_STORE_C>;
 using ProgFwdRe = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_STORE_R>;
 using ProgSmearMid = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_SAVE, ROP_LOOP, ROP_RESTORE, ROP_MUL_RTAB2D,

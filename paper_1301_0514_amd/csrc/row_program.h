@@ -42,6 +42,7 @@ enum RowOpCode : int32_t {
     ROP_ENDLOOP,     // end of the repeated range
     ROP_MUL_ROWTAB,  // v *= tab[row]  (complex, one factor per row)
     ROP_SIDE_T,      // first op only: the launch also runs the transposes of RowProgram::side
+    ROP_ACC_ABS2U,   // acc[e] += |v|^2, no weight (two fused multiply-adds per element)
 };
 
 // Flag bits

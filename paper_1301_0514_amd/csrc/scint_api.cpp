@@ -346,6 +346,7 @@ double row_flops(const RowProgram &p, int n_ops) {
         case ROP_MUL_TAB: case ROP_MUL_ROWTAB: f = 6.0; break;
         case ROP_MUL_RTAB2D: case ROP_MUL_RLOAD: case ROP_DOT_R: f = 2.0; break;
         case ROP_ACC_ABS2: f = 5.0; break;
+        case ROP_ACC_ABS2U: f = 4.0; break;
         case ROP_GRAD_PHI: f = 4.0; break;
         case ROP_SQRT2RE: f = 1.0; break;
         default: break;
@@ -471,7 +472,7 @@ int tune_plan(int N, std::vector<float> *ms_out, int *best) {
         .op(ROP_FFT_FWD)
         .op(ROP_MUL_TAB, H, 0, 0, N)
         .op(ROP_FFT_INV)
-        .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0)
+        .op(ROP_ACC_ABS2U)
         .op(ROP_ENDLOOP)
         .op(ROP_STORE_ACC, Sr, (int64_t)N * N, N);  // row g at g N: inside the scratch
     // rounds over all variants in turn (so drift affects them alike); the
@@ -548,16 +549,29 @@ int transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes, 
 }
 
 // Chirp tables H1(k)/N for n wavelengths with Fresnel radii rho[j] pixels.
-int chirp_tables(void *tab, int N, const std::vector<double> &rho, int dtype, bool normalise, hipStream_t stream) {
+// amp (optional, one per wavelength) multiplies each table.
+int chirp_tables(void *tab, int N, const std::vector<double> &rho, int dtype, bool normalise, hipStream_t stream,
+                 const std::vector<double> *amp = nullptr) {
     const int n = (int)rho.size();
     for (int j0 = 0; j0 < n; j0 += 64) {
         const int m = std::min(64, n - j0);
         double a[64];
         for (int j = 0; j < m; ++j) a[j] = kPiD * rho[j0 + j] * rho[j0 + j] / ((double)N * (double)N);
         char *base = static_cast<char *>(tab) + (size_t)j0 * N * 2 * real_bytes(dtype);
-        HIP_TRY(launch_chirp_tables(base, N, a, m, normalise ? 1.0 / N : 1.0, dtype == PS_F64, stream));
+        HIP_TRY(launch_chirp_tables(base, N, a, m, normalise ? 1.0 / N : 1.0, dtype == PS_F64, stream,
+                                    amp ? amp->data() + j0 : nullptr));
     }
     return PS_OK;
+}
+
+// Weights of the co-added intensities carried by the chirp tables: both 1-D
+// passes multiply by the table of wavelength j, so a factor w_j^(1/4) in it
+// scales the field by sqrt(w_j) and its |.|^2 by w_j, and the accumulation
+// needs no product by the weight.
+static std::vector<double> weight_amps(const std::vector<double> &w, size_t j0, size_t m) {
+    std::vector<double> a(m);
+    for (size_t j = 0; j < m; ++j) a[j] = std::sqrt(std::sqrt(w[j0 + j]));
+    return a;
 }
 
 double f_beta(double beta) { return std::pow(2.0, -beta) * beta * std::tgamma(-beta / 2.0) / std::tgamma(beta / 2.0); }
@@ -895,7 +909,7 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
             .op(ROP_FFT_FWD)
             .op(ROP_MUL_TAB, H)
             .op(ROP_FFT_INV)
-            .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, 0, 1.0)
+            .op(ROP_ACC_ABS2U)
             .op(ROP_ENDLOOP)
             .op(ROP_STORE_ACC, W1, nn(N), N);
         if (int rc = run_row<ProgPropIntensityTag>(dtype, N, d.p, d.n, stream)) return rc;
@@ -912,7 +926,8 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
                       const std::vector<double> &scale, const std::vector<double> &weight, int dtype, void *W1,
                       void *W2, void *H, void *Iacc, bool add, hipStream_t stream) {
     const int C = (int)rho.size();
-    if (int rc = chirp_tables(H, N, rho, dtype, true, stream)) return rc;
+    const std::vector<double> amp = weight_amps(weight, 0, C);
+    if (int rc = chirp_tables(H, N, rho, dtype, true, stream, &amp)) return rc;
     ProgBuilder a(N, (int64_t)nb * N);
     a.p.n_iter = C;
     for (int j = 0; j < C; ++j) a.p.scale[j] = scale[j];
@@ -927,13 +942,12 @@ static int poly_chunk(int N, const void *phi, int nb, const std::vector<double> 
     if (int rc = transpose(W1, W2, N, (int64_t)nb * C, 2 * (int)real_bytes(dtype), stream)) return rc;
     ProgBuilder b(N, (int64_t)nb * N);
     b.p.n_iter = C;
-    for (int j = 0; j < C; ++j) b.p.weight[j] = weight[j];
     b.op(ROP_LOOP)
         .op(ROP_LOAD_C, W2, nn(N), N, (int64_t)nb * nn(N))
         .op(ROP_FFT_FWD)
         .op(ROP_MUL_TAB, H, 0, 0, N)
         .op(ROP_FFT_INV)
-        .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, RF_ITER_WEIGHT)
+        .op(ROP_ACC_ABS2U)
         .op(ROP_ENDLOOP)
         .op(ROP_STORE_ACC, Iacc, nn(N), N, 0, add ? RF_ADD : 0);
     return run_row<ProgPropIntensityTag>(dtype, N, b.p, b.n, stream);
@@ -989,7 +1003,8 @@ static int poly_pipelined(int N, const char *phi_ref, const std::vector<PolyJob>
         if (has_x) {
             const PolyJob &jb = jobs[k];
             std::vector<double> r(rho.begin() + jb.j0, rho.begin() + jb.j0 + jb.m);
-            if (int rc = chirp_tables(H[k % 3], N, r, PS_F32, true, stream)) return rc;
+            const std::vector<double> amp = weight_amps(weight, jb.j0, jb.m);
+            if (int rc = chirp_tables(H[k % 3], N, r, PS_F32, true, stream, &amp)) return rc;
             const bool with_side = has_t && ua > 0;
             ProgBuilder a(N, (int64_t)jb.nb * N);
             a.p.n_iter = jb.m;
@@ -1015,7 +1030,6 @@ static int poly_pipelined(int N, const char *phi_ref, const std::vector<PolyJob>
             const bool with_side = has_t && ua < U;
             ProgBuilder b(N, (int64_t)jb.nb * N);
             b.p.n_iter = jb.m;
-            for (int j = 0; j < jb.m; ++j) b.p.weight[j] = weight[jb.j0 + j];
             if (with_side) {
                 b.op(ROP_SIDE_T);
                 side(b.p.side, ua, U, sc.fft_y, sc.side_y);
@@ -1025,7 +1039,7 @@ static int poly_pipelined(int N, const char *phi_ref, const std::vector<PolyJob>
                 .op(ROP_FFT_FWD)
                 .op(ROP_MUL_TAB, H[(k - 2) % 3], 0, 0, N)
                 .op(ROP_FFT_INV)
-                .op(ROP_ACC_ABS2, nullptr, 0, 0, 0, RF_ITER_WEIGHT)
+                .op(ROP_ACC_ABS2U)
                 .op(ROP_ENDLOOP)
                 .op(ROP_STORE_ACC, Iacc, nn(N), N, 0, jb.j0 > 0 ? RF_ADD : 0);
             const int rc = with_side ? run_row_side<ProgPropIntensityTTag>(N, b.p, b.n, stream)
