@@ -26,6 +26,13 @@
  *    (hipMalloc), later calls of that shape or smaller allocate nothing.  Calls
  *    that overlap on the same stream are ordered by the stream; calls on two
  *    streams use two workspaces.  ps_release_cache() frees everything.
+ *  - Graph capture: a call made while hip_stream is being captured into a
+ *    HIP graph returns PS_E_CAPTURE, before enqueuing anything, if it would
+ *    have to allocate (a first use of a size, radius set or larger batch on
+ *    that stream), tune an FFT plan, copy tables from the host or synchronise
+ *    (entry points returning host values).  Make the same call once before
+ *    the capture, or call ps_tune_plans(); the captured call then enqueues
+ *    kernels only.
  *  - Every entry point returns a ps_status.  Arguments are validated before
  *    anything is launched; on error nothing is written and ps_last_error()
  *    returns a message (thread-local).  PS_E_DEVICE reports a failing HIP call.
@@ -54,7 +61,8 @@ typedef enum {
     PS_E_ALLOC = -5,         /* device memory for the workspace or cache failed */
     PS_E_DEVICE = -6,        /* a HIP call or kernel launch failed              */
     PS_E_ALIAS = -7,         /* output overlaps an input where that is not allowed */
-    PS_E_UNIMPLEMENTED = -8  /* combination the library does not provide       */
+    PS_E_UNIMPLEMENTED = -8, /* combination the library does not provide       */
+    PS_E_CAPTURE = -9        /* would allocate or synchronise during graph capture */
 } ps_status;
 
 /* 1 if N is supported for dtype, else 0.  The FP32 set is
@@ -333,10 +341,16 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype,
  *                         ps_num_plan_variants(N, dtype) floats, receives the
  *                         tuner's times (-1 where not timed)
  *   ps_set_plan_variant   pins plan `variant`, or -1 to return to tuning
+ *   ps_tune_plans         chooses the plan of N (tuning it if needed) and
+ *                         builds its twiddle table on the current device,
+ *                         synchronously on the null stream, so that no later
+ *                         call of size N tunes or builds tables: call it
+ *                         before capturing a graph that uses size N
  */
 int ps_num_plan_variants(int N, int dtype);
 int ps_plan_variant(int N, int dtype, int *variant_out, float *ms_out);
 int ps_set_plan_variant(int N, int dtype, int variant);
+int ps_tune_plans(int N, int dtype);
 
 /*
  * ps_set_workspace_budget -- upper bound, in bytes, on the workspace that
@@ -369,12 +383,25 @@ int ps_plan_polychromatic(int N, int n_real, int n_lambda, int dtype, size_t bud
  * Kernel timing (instrumentation).  While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the stream it runs on,
  * and per kernel name the library accumulates the event-measured duration,
- * the launch count, the algorithmic bytes of each launch (the elements the
- * kernel's operations must read and write, summed over its rows: complex
- * elements count 2 reals; the 1-D chirp tables are not counted) and its
- * algorithmic floating-point operations (5 N log2 N per length-N complex DFT,
- * 6 per complex multiply, 2 per real-by-complex multiply, 5 per weighted
- * |A|^2 accumulation; sine, cosine and the noise generator not counted).
+ * the launch count, and per launch:
+ *   bytes           algorithmic bytes: each array the method reads or writes
+ *                   in that pass, once (complex elements count 2 reals; an
+ *                   array re-read on every loop iteration at the same
+ *                   address, such as the phase screen re-read for each
+ *                   wavelength, once; the 1-D chirp tables not at all; the
+ *                   transposes between the two 1-D passes of a 2-D transform
+ *                   zero, since the method's one exchange per transform is
+ *                   the first pass's write and the second pass's read);
+ *   schedule_bytes  the operand bytes of the launch as scheduled: every
+ *                   access of the kernel's operations, loop re-reads
+ *                   included, plus 16 bytes per element of the transposes a
+ *                   row pass carries or 2 x element size per element of a
+ *                   transpose kernel;
+ *   flops           algorithmic floating-point operations (5 N log2 N per
+ *                   length-N complex DFT, 6 per complex multiply, 2 per
+ *                   real-by-complex multiply, 5 per weighted |A|^2
+ *                   accumulation; sine, cosine and the noise generator not
+ *                   counted).
  *   ps_timing_enable(1) clears the totals and starts recording; (0) stops.
  *   ps_timing_count() waits for the recorded events and returns the number
  *   of distinct kernel names; ps_timing_entry(i, ...) returns the i-th
@@ -383,7 +410,7 @@ int ps_plan_polychromatic(int N, int n_real, int n_lambda, int dtype, size_t bud
 int ps_timing_enable(int on);
 int ps_timing_count(void);
 int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches,
-                    double *bytes, double *flops);
+                    double *bytes, double *schedule_bytes, double *flops);
 
 /* Message for the last non-OK status of this thread ("" if none). */
 const char *ps_last_error(void);

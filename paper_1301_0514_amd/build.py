@@ -1,16 +1,20 @@
 """Build libscint.so (the gfx950 HIP library) in-tree with hipcc.
 
-Usage: python -m paper_1301_0514_amd.build [--jobs N] [--verbose]
+Usage: python -m paper_1301_0514_amd.build [--jobs N] [--verbose] [--incremental]
 
 Compiles the row-pass kernel once per (precision, program), the auxiliary
 kernels and the host C ABI, and links them into
-paper_1301_0514_amd/lib/libscint.so.  Every call rebuilds from scratch.
+paper_1301_0514_amd/lib/libscint.so.  Every call rebuilds from scratch unless
+--incremental is given, which recompiles only the objects older than a source
+they include (quoted #include files, followed recursively) or built with
+other flags.
 """
 from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -52,10 +56,36 @@ def _jobs() -> list[tuple[list[str], str]]:
     return jobs
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _deps(src: str, seen=None) -> set:
+    """src and every file it includes with #include "...", recursively."""
+    seen = set() if seen is None else seen
+    src = os.path.normpath(src)
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    with open(src, errors="replace") as fh:
+        for name in re.findall(r'^\s*#\s*include\s+"([^"]+)"', fh.read(), flags=re.M):
+            _deps(os.path.join(os.path.dirname(src), name), seen)
+    return seen
+
+
+def _up_to_date(cmd: list, obj: str) -> bool:
+    stamp = obj + ".cmd"
+    if not (os.path.exists(obj) and os.path.exists(stamp)):
+        return False
+    with open(stamp) as fh:
+        if fh.read() != " ".join(cmd):
+            return False
+    src = cmd[cmd.index("-c") + 1]
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(d) < t for d in _deps(src))
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
     if jobs is None:
         jobs = int(os.environ.get("MAX_JOBS", "0")) or min(16, os.cpu_count() or 4)
-    shutil.rmtree(BUILD, ignore_errors=True)
+    if not incremental:
+        shutil.rmtree(BUILD, ignore_errors=True)
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
     t0 = time.time()
@@ -63,9 +93,13 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
     def run(item):
         cmd, obj = item
+        if incremental and _up_to_date(cmd, obj):
+            return obj
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+        with open(obj + ".cmd", "w") as fh:
+            fh.write(" ".join(cmd))
         if verbose:
             print("built", os.path.basename(obj), flush=True)
         return obj
@@ -87,8 +121,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args(argv)
-    build(a.jobs, a.verbose)
+    build(a.jobs, a.verbose, a.incremental)
     return 0
 
 

@@ -113,6 +113,28 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
+// True if `stream` is being captured into a graph.  A failing query (the
+// null stream while another stream captures in global mode) counts as
+// capturing; its error is cleared so that later launch checks do not see it.
+bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return st != hipStreamCaptureStatusNone;
+}
+
+// PS_E_CAPTURE if `stream` is being captured: called where a call would
+// allocate device memory, copy from the host or synchronise, none of which a
+// captured graph may contain.
+int refuse_in_capture(hipStream_t stream, const char *what) {
+    if (!capturing(stream)) return PS_OK;
+    return fail(PS_E_CAPTURE, std::string(what) +
+                                  " would allocate or synchronise while the stream is being captured: run the "
+                                  "same call once before the capture (or ps_tune_plans for the FFT plans)");
+}
+
 // ------------------------------------------------------------ device caches
 struct DeviceCache {
     std::map<std::tuple<int, int, int>, void *> twiddles;  // (L, variant, dtype) -> table
@@ -134,7 +156,7 @@ int current_device(int *dev) {
 }
 
 // Twiddle table of plan (L, V) in the working precision.
-int get_twiddles(int L, int V, int dtype, const void **out) {
+int get_twiddles(int L, int V, int dtype, const void **out, hipStream_t stream) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
     std::lock_guard<std::mutex> lock(g_mutex);
@@ -145,6 +167,7 @@ int get_twiddles(int L, int V, int dtype, const void **out) {
         *out = it->second;
         return PS_OK;
     }
+    if (int rc = refuse_in_capture(stream, "building an FFT twiddle table")) return rc;
     const int n = twiddle_entries(L, V);
     std::vector<double> ri(2 * (size_t)std::max(n, 1));
     if (n > 0 && !build_twiddles(L, V, ri.data())) return fail(PS_E_SIZE, "no FFT plan for this size");
@@ -175,6 +198,7 @@ int get_workspace(hipStream_t stream, size_t bytes, void **out) {
     std::lock_guard<std::mutex> lock(g_mutex);
     auto &ws = g_cache[dev].workspace[stream];
     if (ws.second < bytes) {
+        if (int rc = refuse_in_capture(stream, "growing the workspace")) return rc;
         if (ws.first) {
             // work queued on this stream may still use the old buffer
             HIP_TRY(hipStreamSynchronize(stream));
@@ -208,12 +232,13 @@ struct Carver {
 struct PendingTiming {
     std::string name;
     hipEvent_t start, stop;
-    double bytes, flops;
+    double bytes, sched_bytes, flops;
 };
 struct TimingTotal {
     double ms = 0.0;
     long long launches = 0;
-    double bytes = 0.0;
+    double bytes = 0.0;        // algorithmic bytes (each operand of the method moved once)
+    double sched_bytes = 0.0;  // operand bytes of the schedule as launched
     double flops = 0.0;
 };
 std::mutex g_timing_mutex;
@@ -246,7 +271,8 @@ bool timing_begin(hipStream_t stream, hipEvent_t *start) {
     return true;
 }
 
-void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, double bytes, double flops) {
+void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, double bytes, double sched_bytes,
+                double flops) {
     std::lock_guard<std::mutex> lock(g_timing_mutex);
     hipEvent_t stop = pool_event();
     if (!stop) return;
@@ -254,7 +280,7 @@ void timing_end(hipStream_t stream, hipEvent_t start, const std::string &name, d
         g_event_pool.push_back(stop);
         return;
     }
-    g_pending.push_back({name, start, stop, bytes, flops});
+    g_pending.push_back({name, start, stop, bytes, sched_bytes, flops});
 }
 
 void timing_drain() {
@@ -266,6 +292,7 @@ void timing_drain() {
             t.ms += ms;
             t.launches += 1;
             t.bytes += p.bytes;
+            t.sched_bytes += p.sched_bytes;
             t.flops += p.flops;
         }
         g_event_pool.push_back(p.start);
@@ -305,9 +332,15 @@ struct ProgBuilder {
     }
 };
 
-// Algorithmic bytes of one row-pass launch: per element of a row, what each
-// operation reads or writes (ops inside the loop once per iteration).
-double row_bytes(const RowProgram &p, int n_ops, int dtype) {
+// Bytes of one row-pass launch, per element of a row summed over its rows.
+// Schedule bytes (algorithmic = false): every operand access as the
+// program makes it, those inside the loop once per iteration.  Algorithmic
+// bytes (algorithmic = true): each array the method must read or write,
+// once -- an operand inside the loop counts once per iteration only if its
+// address moves with the iteration (a phase screen re-read for every
+// wavelength counts once).  The 1-D chirp tables and row factors are not
+// counted by either.
+double row_bytes(const RowProgram &p, int n_ops, int dtype, bool algorithmic) {
     const double rb = (double)real_bytes(dtype);
     double per = 0.0;
     bool in_loop = false;
@@ -324,7 +357,8 @@ double row_bytes(const RowProgram &p, int n_ops, int dtype) {
         case ROP_STORE_ACC: b = (o.flags & RF_ADD) ? 2 * rb : rb; break;
         default: break;
         }
-        per += in_loop ? b * p.n_iter : b;
+        const bool per_iter = in_loop && (!algorithmic || o.iter_stride != 0);
+        per += per_iter ? b * p.n_iter : b;
     }
     return per * (double)p.N * (double)p.total_rows;
 }
@@ -380,13 +414,13 @@ SCINT_PROG_NAME(ProgSmearMidT)
 SCINT_PROG_NAME(ProgInvReT)
 #undef SCINT_PROG_NAME
 
-int plan_variant(int N, int dtype, int *V);
+int plan_variant(int N, int dtype, int *V, hipStream_t stream);
 
 template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_ops, hipStream_t stream) {
     int V = 0;
-    if (int rc = plan_variant(N, dtype, &V)) return rc;
+    if (int rc = plan_variant(N, dtype, &V, stream)) return rc;
     const void *tw = nullptr;
-    if (int rc = get_twiddles(N, V, dtype, &tw)) return rc;
+    if (int rc = get_twiddles(N, V, dtype, &tw, stream)) return rc;
     hipEvent_t t0 = nullptr;
     const bool timed = timing_begin(stream, &t0);
     hipError_t e = dtype == PS_F64 ? launch_row<double, Tag>(N, V, p, tw, stream)
@@ -395,7 +429,7 @@ template <class Tag> int run_row(int dtype, int N, const RowProgram &p, int n_op
     if (timed)
         timing_end(stream, t0,
                    std::string("row_") + prog_name<Tag>() + "_" + real_name(dtype) + "_N" + std::to_string(N),
-                   row_bytes(p, n_ops, dtype), row_flops(p, n_ops));
+                   row_bytes(p, n_ops, dtype, true), row_bytes(p, n_ops, dtype, false), row_flops(p, n_ops));
     return PS_OK;
 }
 
@@ -419,20 +453,21 @@ double side_elements(const RowSide &sd, int N) {
 }
 
 // Row pass whose launch also runs the transposes of p.side (FP32 programs
-// only).  Its timing entry counts their bytes too (each element read once
-// and written once).
+// only).  Its timing entry counts their bytes among the schedule's (each
+// element read once and written once), not among the algorithmic ones.
 template <class Tag> int run_row_side(int N, const RowProgram &p, int n_ops, hipStream_t stream) {
     int V = 0;
-    if (int rc = plan_variant(N, PS_F32, &V)) return rc;
+    if (int rc = plan_variant(N, PS_F32, &V, stream)) return rc;
     const void *tw = nullptr;
-    if (int rc = get_twiddles(N, V, PS_F32, &tw)) return rc;
+    if (int rc = get_twiddles(N, V, PS_F32, &tw, stream)) return rc;
     hipEvent_t t0 = nullptr;
     const bool timed = timing_begin(stream, &t0);
     hipError_t e = launch_row<float, Tag>(N, V, p, tw, stream);
     if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("row pass launch: ") + hipGetErrorString(e));
     if (timed)
         timing_end(stream, t0, std::string("row_") + prog_name<Tag>() + "_f32_N" + std::to_string(N),
-                   row_bytes(p, n_ops, PS_F32) + 16.0 * side_elements(p.side, N), row_flops(p, n_ops));
+                   row_bytes(p, n_ops, PS_F32, true),
+                   row_bytes(p, n_ops, PS_F32, false) + 16.0 * side_elements(p.side, N), row_flops(p, n_ops));
     return PS_OK;
 }
 
@@ -479,7 +514,7 @@ int tune_plan(int N, std::vector<float> *ms_out, int *best) {
     // first round warms up, then the minimum over the timed rounds counts
     ms_out->assign(nv, 1e30f);
     std::vector<const void *> tws(nv, nullptr);
-    for (int v = 0; v < nv && !rc; ++v) rc = get_twiddles(N, v, PS_F32, &tws[v]);
+    for (int v = 0; v < nv && !rc; ++v) rc = get_twiddles(N, v, PS_F32, &tws[v], s);
     for (int r = 0; r < 6 && !rc; ++r) {
         for (int v = 0; v < nv && !rc; ++v) {
             (void)hipEventRecord(a, s);
@@ -507,7 +542,7 @@ int tune_plan(int N, std::vector<float> *ms_out, int *best) {
     return PS_OK;
 }
 
-int plan_variant(int N, int dtype, int *V) {
+int plan_variant(int N, int dtype, int *V, hipStream_t stream) {
     *V = 0;
     if (dtype == PS_F64 || plan_variants(N) == 1) return PS_OK;
     int dev;
@@ -528,8 +563,10 @@ int plan_variant(int N, int dtype, int *V) {
         if (v >= 0 && v < plan_variants(N)) chosen = v;
     }
     std::vector<float> ms;
-    if (chosen < 0)
+    if (chosen < 0) {
+        if (int rc = refuse_in_capture(stream, "tuning the FFT plan of this size")) return rc;
         if (int rc = tune_plan(N, &ms, &chosen)) return rc;
+    }
     std::lock_guard<std::mutex> lock(g_mutex);
     auto &dc = g_cache[dev];
     dc.variant[key] = chosen;
@@ -543,7 +580,7 @@ int transpose(const void *in, void *out, int N, int64_t nbatch, int elem_bytes, 
     const bool timed = timing_begin(stream, &t0);
     HIP_TRY(launch_transpose(in, out, N, nbatch, elem_bytes, stream));
     if (timed)
-        timing_end(stream, t0, "transpose_" + std::to_string(elem_bytes) + "B_N" + std::to_string(N),
+        timing_end(stream, t0, "transpose_" + std::to_string(elem_bytes) + "B_N" + std::to_string(N), 0.0,
                    2.0 * elem_bytes * (double)N * N * (double)nbatch, 0.0);
     return PS_OK;
 }
@@ -705,7 +742,7 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
 // ============================================================ C ABI
 extern "C" {
 
-int ps_version(void) { return 10000; }
+int ps_version(void) { return 10100; }
 
 int ps_num_plan_variants(int N, int dtype) {
     if (dtype == PS_F64) return supported_f64(N) ? 1 : 0;
@@ -718,7 +755,7 @@ int ps_plan_variant(int N, int dtype, int *variant_out, float *ms_out) {
     if (int rc = check_common(N, dtype, 1)) return rc;
     if (!variant_out) return fail(PS_E_NULL, "variant_out is NULL");
     int V = 0;
-    if (int rc = plan_variant(N, dtype, &V)) return rc;
+    if (int rc = plan_variant(N, dtype, &V, nullptr)) return rc;
     *variant_out = V;
     if (ms_out) {
         int dev = 0;
@@ -749,6 +786,15 @@ int ps_set_plan_variant(int N, int dtype, int variant) {
     return PS_OK;
 }
 
+int ps_tune_plans(int N, int dtype) {
+    g_last_error.clear();
+    if (int rc = check_common(N, dtype, 1)) return rc;
+    int V = 0;
+    if (int rc = plan_variant(N, dtype, &V, nullptr)) return rc;
+    const void *tw = nullptr;
+    return get_twiddles(N, V, dtype, &tw, nullptr);
+}
+
 int ps_set_workspace_budget(size_t bytes) {
     g_last_error.clear();
     if (bytes != 0 && bytes < ((size_t)64 << 20)) return fail(PS_E_PARAM, "workspace budget below 64 MiB");
@@ -774,7 +820,7 @@ int ps_timing_count(void) {
 }
 
 int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long long *launches, double *bytes,
-                    double *flops) {
+                    double *schedule_bytes, double *flops) {
     std::lock_guard<std::mutex> lock(g_timing_mutex);
     if (i < 0 || i >= (int)g_totals.size()) return fail(PS_E_SIZE, "timing entry index out of range");
     auto it = g_totals.begin();
@@ -786,6 +832,7 @@ int ps_timing_entry(int i, char *name_buf, int buf_len, double *total_ms, long l
     if (total_ms) *total_ms = it->second.ms;
     if (launches) *launches = it->second.launches;
     if (bytes) *bytes = it->second.bytes;
+    if (schedule_bytes) *schedule_bytes = it->second.sched_bytes;
     if (flops) *flops = it->second.flops;
     return PS_OK;
 }
@@ -1341,6 +1388,7 @@ static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hi
             return PS_OK;
         }
     }
+    if (int rc = refuse_in_capture(stream, "building the disk spectra of these radii")) return rc;
     const size_t rb = (size_t)nn(N) * real_bytes(dtype);
     const size_t cb = 2 * rb;
     void *block = nullptr;
@@ -1587,6 +1635,8 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
     if (overlaps(grad_phi_out, rb1 * n, phi, rb1 * n) || overlaps(grad_phi_out, rb1 * n, grad_I, rb1 * n))
         return fail(PS_E_ALIAS, "grad_phi_out overlaps phi or grad_I");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (phi_dot_grad_out)
+        if (int rc = refuse_in_capture(stream, "returning phi_dot_grad_out to the host")) return rc;
     const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
     const size_t cbytes = 2 * rb1;
     const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
@@ -1670,6 +1720,7 @@ int ps_modulation_index(int N, const void *I, int n, int dtype, double *m_out, d
     if (!I || !m_out) return fail(PS_E_NULL, "I and m_out must be non-NULL");
     if (int rc = check_aligned({I})) return rc;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (int rc = refuse_in_capture(stream, "ps_modulation_index")) return rc;
     const int64_t per = nn(N);
     const int nblk = block_count(per);
     void *ws = nullptr;
@@ -1705,6 +1756,7 @@ int ps_modulation_index_region(int N, const void *I, int n, int x0, int y0, int 
     if (x0 < 0 || y0 < 0 || w < 1 || h < 1 || w > N - x0 || h > N - y0)
         return fail(PS_E_PARAM, "the region must be non-empty and lie inside the N x N image");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (int rc = refuse_in_capture(stream, "ps_modulation_index_region")) return rc;
     const int64_t count = (int64_t)w * h;
     const int nblk = block_count(count);
     void *ws = nullptr;
@@ -1746,6 +1798,8 @@ int ps_light_curves(int N, const void *I, int n, const double *lines, int n_line
     const size_t cb = (size_t)n * n_lines * n_samples * real_bytes(dtype);
     if (overlaps(I, ib, curves_out, cb)) return fail(PS_E_ALIAS, "curves_out overlaps I");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (m_out)
+        if (int rc = refuse_in_capture(stream, "returning m_out to the host")) return rc;
     double *stats = nullptr;
     if (m_out) {
         void *ws = nullptr;
@@ -1788,6 +1842,7 @@ int ps_structure_function(int N, double delta, const void *phi, int n, const dou
     for (int j = 0; j < n_r; ++j)
         if (!(std::isfinite(radii[j]) && radii[j] >= 0.0)) return fail(PS_E_PARAM, "radii must be finite and >= 0");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (int rc = refuse_in_capture(stream, "ps_structure_function")) return rc;
     const int nbins = N / 2 + 1;
     const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
     const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
@@ -1847,6 +1902,8 @@ int ps_l2_loss(int N, const void *I, const void *I_target, int n, int dtype, voi
     if (grad_out && (overlaps(grad_out, rb, I, rb) || overlaps(grad_out, rb, I_target, rb)))
         return fail(PS_E_ALIAS, "grad_out overlaps I or I_target");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (loss_out)
+        if (int rc = refuse_in_capture(stream, "returning loss_out to the host")) return rc;
     const int64_t per = nn(N);
     const int nblk = block_count(per);
     void *ws = nullptr;

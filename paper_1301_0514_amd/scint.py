@@ -22,7 +22,9 @@ LIB_PATH = os.path.join(_HERE, "lib", "libscint.so")
 PS_F32, PS_F64 = 0, 1
 PS_OK = 0
 STATUS_NAMES = {0: "PS_OK", -1: "PS_E_NULL", -2: "PS_E_SIZE", -3: "PS_E_PARAM", -4: "PS_E_DTYPE",
-                -5: "PS_E_ALLOC", -6: "PS_E_DEVICE", -7: "PS_E_ALIAS", -8: "PS_E_UNIMPLEMENTED"}
+                -5: "PS_E_ALLOC", -6: "PS_E_DEVICE", -7: "PS_E_ALIAS", -8: "PS_E_UNIMPLEMENTED",
+                -9: "PS_E_CAPTURE"}
+PS_E_CAPTURE = -9
 
 # Every symbol include/scint.h declares, with its ctypes signature.
 _c_int, _c_dbl, _c_u32, _c_u64, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
@@ -57,6 +59,7 @@ SIGNATURES = {
     "ps_num_plan_variants": (_c_int, [_c_int, _c_int]),
     "ps_plan_variant": (_c_int, [_c_int, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_float)]),
     "ps_set_plan_variant": (_c_int, [_c_int, _c_int, _c_int]),
+    "ps_tune_plans": (_c_int, [_c_int, _c_int]),
     "ps_set_workspace_budget": (_c_int, [ctypes.c_size_t]),
     "ps_plan_polychromatic": (_c_int, [_c_int, _c_int, _c_int, _c_int, ctypes.c_size_t, ctypes.POINTER(_c_int),
                                        ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
@@ -64,7 +67,7 @@ SIGNATURES = {
     "ps_timing_enable": (_c_int, [_c_int]),
     "ps_timing_count": (_c_int, []),
     "ps_timing_entry": (_c_int, [_c_int, ctypes.c_char_p, _c_int, _dp, ctypes.POINTER(ctypes.c_longlong), _dp,
-                                 _dp]),
+                                 _dp, _dp]),
 }
 
 _lock = threading.Lock()
@@ -137,6 +140,20 @@ def _batch_of(t: torch.Tensor, N: int) -> int:
     return t.numel() // (N * N)
 
 
+def _check_like(name: str, t: torch.Tensor, shape, dtype: torch.dtype, device: torch.device) -> None:
+    """Raise ValueError unless t has exactly the shape, dtype and device the
+    library will write or read through it (the C ABI trusts the sizes it is
+    given, so a smaller or differently typed buffer would be overrun)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.device != device:
+        raise ValueError("%s must be on %s, got %s" % (name, device, t.device))
+
+
 # ------------------------------------------------------------------ queries
 def supported_size(N: int, dtype: torch.dtype = torch.float32) -> bool:
     return bool(load_library().ps_supported_size(int(N), _dtype_code(dtype)))
@@ -179,6 +196,13 @@ def set_plan_variant(N: int, variant: int, dtype: torch.dtype = torch.float32) -
     _check("ps_set_plan_variant", load_library().ps_set_plan_variant(int(N), _dtype_code(dtype), int(variant)))
 
 
+def tune_plans(N: int, dtype: torch.dtype = torch.float32) -> None:
+    """Choose (tuning if needed) the FFT plan of size N and build its tables on
+    the current device, so that a later graph capture of size-N calls finds
+    nothing to allocate or time."""
+    _check("ps_tune_plans", load_library().ps_tune_plans(int(N), _dtype_code(dtype)))
+
+
 def set_workspace_budget(nbytes: int, device=None) -> None:
     """Cap the workspace the library plans for on `device` (default: the
     current one) at nbytes; 0 restores the default."""
@@ -208,16 +232,19 @@ def timing_enable(on: bool = True) -> None:
 
 
 def timing_report() -> dict:
-    """{kernel name: {"ms": total, "launches": n, "bytes": algorithmic bytes, "flops": ...}}
-    for the kernels launched while timing was enabled (waits for them)."""
+    """{kernel name: {"ms": total, "launches": n, "bytes": algorithmic bytes,
+    "schedule_bytes": operand bytes as scheduled, "flops": ...}} for the
+    kernels launched while timing was enabled (waits for them)."""
     lib = load_library()
     out = {}
     for i in range(lib.ps_timing_count()):
         buf = ctypes.create_string_buffer(256)
-        ms, n, b, f = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        b, sb, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check("ps_timing_entry", lib.ps_timing_entry(i, buf, 256, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
-                                                      ctypes.byref(f)))
-        out[buf.value.decode()] = {"ms": ms.value, "launches": n.value, "bytes": b.value, "flops": f.value}
+                                                      ctypes.byref(sb), ctypes.byref(f)))
+        out[buf.value.decode()] = {"ms": ms.value, "launches": n.value, "bytes": b.value,
+                                   "schedule_bytes": sb.value, "flops": f.value}
     return out
 
 
@@ -228,6 +255,9 @@ def ps_generate(N, delta, r_diff, beta, seed, first_realisation=0, n_real=1, dty
     device = torch.device(device or "cuda")
     if out is None:
         out = torch.empty((n_real, N, N), dtype=dtype, device=device)
+    else:
+        _check_like("out", out, (n_real, N, N), out.dtype, out.device)
+        _dtype_code(out.dtype)
     rc = load_library().ps_generate(int(N), float(delta), float(r_diff), float(beta), int(seed),
                                     int(first_realisation), int(n_real), _dtype_code(out.dtype),
                                     _ptr(out), _stream(out.device))
@@ -242,6 +272,8 @@ def fresnel_propagate(phi: torch.Tensor, delta, lam, z, phase_scale=1.0,
     n = _batch_of(phi, N)
     if out is None:
         out = torch.empty_like(phi)
+    else:
+        _check_like("out", out, phi.shape, phi.dtype, phi.device)
     rc = load_library().fresnel_propagate(int(N), float(delta), float(lam), float(z), _ptr(phi),
                                           float(phase_scale), n, _dtype_code(phi.dtype), _ptr(out),
                                           _stream(phi.device))
@@ -257,6 +289,8 @@ def fresnel_aperture(phi: torch.Tensor, delta, lam, z, phase_scale=1.0, margin_r
     n = _batch_of(phi, N)
     if out is None:
         out = torch.empty_like(phi)
+    else:
+        _check_like("out", out, phi.shape, phi.dtype, phi.device)
     rc = load_library().fresnel_aperture(int(N), float(delta), float(lam), float(z), _ptr(phi), float(phase_scale),
                                          float(margin_rf), n, _dtype_code(phi.dtype), _ptr(out), _stream(phi.device))
     _check("fresnel_aperture", rc)
@@ -294,6 +328,8 @@ def illumination_polychromatic(phi_ref: torch.Tensor, delta, z, lam_ref, lambdas
     n = _batch_of(phi_ref, N)
     if out is None:
         out = torch.empty_like(phi_ref)
+    else:
+        _check_like("out", out, phi_ref.shape, phi_ref.dtype, phi_ref.device)
     lam = _host_doubles(lambdas)
     w = None if weights is None else _host_doubles(weights)
     if w is not None and len(weights) != len(lambdas):
@@ -311,6 +347,8 @@ def source_smear(I: torch.Tensor, delta, radii, out: torch.Tensor | None = None)
     n = _batch_of(I, N)
     if out is None:
         out = torch.empty((n, len(radii), N, N), dtype=I.dtype, device=I.device)
+    else:
+        _check_like("out", out, (n, len(radii), N, N), I.dtype, I.device)
     rc = load_library().source_smear(int(N), float(delta), _ptr(I), _host_doubles(radii), len(radii), n,
                                      _dtype_code(I.dtype), _ptr(out), _stream(I.device))
     _check("source_smear", rc)
@@ -322,10 +360,11 @@ def fresnel_propagate_vjp(phi: torch.Tensor, delta, lam, z, grad_I: torch.Tensor
     """dL/dphi for dL/dI = grad_I; optionally also sum(phi * dL/dphi) per screen."""
     N = phi.shape[-1]
     n = _batch_of(phi, N)
-    if grad_I.shape != phi.shape or grad_I.dtype != phi.dtype:
-        raise ValueError("grad_I must match phi in shape and dtype")
+    _check_like("grad_I", grad_I, phi.shape, phi.dtype, phi.device)
     if out is None:
         out = torch.empty_like(phi)
+    else:
+        _check_like("out", out, phi.shape, phi.dtype, phi.device)
     dots = (ctypes.c_double * n)() if want_dot else None
     rc = load_library().fresnel_propagate_vjp(int(N), float(delta), float(lam), float(z), _ptr(phi),
                                               float(phase_scale), _ptr(grad_I), n, _dtype_code(phi.dtype),
@@ -414,6 +453,7 @@ def ps_l2_loss(I: torch.Tensor, I_target: torch.Tensor, want_grad=True):
     """L = sum (I - I_t)^2 per pattern and dL/dI = 2 (I - I_t)."""
     N = I.shape[-1]
     n = _batch_of(I, N)
+    _check_like("I_target", I_target, I.shape, I.dtype, I.device)
     grad = torch.empty_like(I) if want_grad else None
     loss = (ctypes.c_double * n)()
     rc = load_library().ps_l2_loss(int(N), _ptr(I), _ptr(I_target), n, _dtype_code(I.dtype), _ptr(grad), loss,

@@ -122,3 +122,36 @@ def test_alignment_rejected(lib):
     assert lib.ps_generate(256, 1.0, 4.0, 11 / 3, 1, 0, 1, 0, _vp((1 << 20) + 4), None) == -3
     assert lib.fresnel_propagate(256, 1.0, 1.0, 1.0, _vp(1 << 20), 1.0, 1, 0, _vp((1 << 30) + 8), None) == -3
     assert b"aligned" in lib.ps_last_error()
+
+
+def test_binding_rejects_mismatched_buffers():
+    """The binding checks every caller-supplied output (and the target of the
+    loss) against what the C call will write or read, before any pointer
+    reaches the library; CPU tensors suffice, since the check comes first."""
+    import torch
+    from paper_1301_0514_amd import scint
+    N = 16
+    phi = torch.zeros((2, N, N), dtype=torch.float32)
+    bad = [torch.zeros((1, N, N), dtype=torch.float32),       # too few screens
+           torch.zeros((2, N, N), dtype=torch.float64),       # wrong precision
+           torch.zeros((2, N, 2 * N), dtype=torch.float32)]   # wrong grid
+    calls = [
+        lambda o: scint.fresnel_propagate(phi, 1.0, 5e-7, 1.0, out=o),
+        lambda o: scint.fresnel_aperture(phi, 1.0, 5e-7, 1.0, out=o),
+        lambda o: scint.illumination_polychromatic(phi, 1.0, 1.0, 5e-7, [5e-7], out=o),
+        lambda o: scint.fresnel_propagate_vjp(phi, 1.0, 5e-7, 1.0, phi, out=o),
+        lambda o: scint.fresnel_propagate_vjp(phi, 1.0, 5e-7, 1.0, o),
+        lambda o: scint.ps_l2_loss(phi, o),
+    ]
+    for call in calls:
+        for o in bad:
+            with pytest.raises(ValueError, match="must"):
+                call(o)
+    with pytest.raises(ValueError, match="shape"):
+        scint.source_smear(phi, 1.0, [1.0, 2.0], out=torch.zeros((2, 1, N, N)))
+    with pytest.raises(ValueError, match="shape"):
+        scint.ps_generate(N, 1.0, 4.0, 11 / 3, 1, 0, 3, out=torch.zeros((2, N, N)))
+    # a matching CPU buffer passes the check and is then refused for living
+    # on the host
+    with pytest.raises(ValueError, match="GPU"):
+        scint.fresnel_propagate(phi, 1.0, 5e-7, 1.0, out=torch.zeros_like(phi))

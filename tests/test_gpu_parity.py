@@ -320,3 +320,46 @@ def test_graph_replay_matches_eager(S):
         # eager work between replays
         S.ps_screen_fresnel(128, 1.0, 3.0, 11 / 3, 1, 5e-7, 1e4)
         torch.cuda.synchronize()
+
+
+def test_cold_call_under_capture_returns_status(S, oracle):
+    """A first call of a size (tables to build, workspace to allocate) made
+    while its stream is being captured returns PS_E_CAPTURE and enqueues
+    nothing; so do entry points that return host values.  After one call
+    outside the capture, the same call captures and its replays equal the
+    oracle's pattern."""
+    N, rho = 320, 20.0
+    z = 2 * np.pi * rho ** 2 / 5e-7
+    phi = dev(inputs.smooth_phase_field(N, seed=3, sigma=2.0, corr=4.0), torch.float32)
+    out = torch.empty_like(phi)
+    S.release_cache()
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(S.ScintError) as e:
+        with torch.cuda.graph(g, stream=stream):
+            out.zero_()
+            S.fresnel_propagate(phi, 1.0, 5e-7, z, out=out)
+    assert e.value.code == S.PS_E_CAPTURE
+    g2 = torch.cuda.CUDAGraph()
+    with pytest.raises(S.ScintError) as e:
+        with torch.cuda.graph(g2, stream=stream):
+            out.zero_()
+            S.ps_modulation_index(phi)
+    assert e.value.code == S.PS_E_CAPTURE
+    # warm on the capture stream, then capture and replay
+    S.tune_plans(N)
+    with torch.cuda.stream(stream):
+        S.fresnel_propagate(phi, 1.0, 5e-7, z, out=out)
+    stream.synchronize()
+    g3 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g3, stream=stream):
+        S.fresnel_propagate(phi, 1.0, 5e-7, z, out=out)
+    I_ref = oracle.propagate(host(phi)[0], rho)
+    for rep in range(2):
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g3.replay()
+        stream.synchronize()
+        d = host(out)[0] - I_ref
+        assert np.sqrt(np.mean(d * d)) / I_ref.mean() < F32_RMS, rep
