@@ -66,6 +66,18 @@ struct RadiusSet {
 hipError_t launch_hankel(const double *S, int N, int nbatch, const double *radii, int n_r, double *D, double *rdiff,
                          hipStream_t stream);
 
+// The lowest Fourier modes of FP32 screens, synthesised in FP64 (Sect. 3.1):
+// for realisations r0 + b, b < nbatch, with W = 2K + 1,
+//   C[b][i][j] = c(kx' = i - K, ky' = j - K), the FP64 spectrum coefficient
+//                (Philox counter (kx, ky, r, 0), key (seed_lo, seed_hi)),
+//   G[b][y][k] = sqrt(2) (B(k) + conj(B(-k))) for 1 <= k <= K, sqrt(2) B(0)
+//                for k = 0, B(kx') = sum_{|ky'| <= K} c(kx', ky') exp(2 pi i ky' y / N),
+// so that sqrt(2) Re of their part of the inverse DFT is
+// Re sum_k G[b][y][k] exp(2 pi i k x / N).  C is scratch (nbatch W^2
+// complex doubles); G is [nbatch][N][K + 1] complex doubles.  K < N/2.
+hipError_t launch_low_modes(void *C, void *G, int N, int K, int nbatch, uint32_t r0, uint32_t seed_lo,
+                            uint32_t seed_hi, double amp0, double neg_beta_4, hipStream_t stream);
+
 // out[b] = scale * sum_blk partials[b * nblk + blk], fixed-order tree.
 hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,
                                 hipStream_t stream);

@@ -79,6 +79,81 @@ hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, in
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------- low modes
+struct LowModeArgs {
+    int N, K;
+    uint32_t r0, seed_lo, seed_hi;
+    double amp0, neg_beta_4;
+};
+
+// C[b][i][j]: one workgroup per (i, b), thread j
+__global__ __launch_bounds__(64) void low_mode_coeff_kernel(double2 *C, LowModeArgs a) {
+    const int W = 2 * a.K + 1;
+    const int i = blockIdx.x, b = blockIdx.y, j = threadIdx.x;
+    if (j >= W) return;
+    const int fx = i - a.K, fy = j - a.K;
+    const int kx = fx < 0 ? fx + a.N : fx, ky = fy < 0 ? fy + a.N : fy;
+    C[((int64_t)b * W + i) * W + j] =
+        spectrum_coeff_f64(kx, ky, a.N, a.r0 + (uint32_t)b, a.seed_lo, a.seed_hi, a.amp0, a.neg_beta_4);
+}
+
+// G[b][y][k]: one workgroup per (y, b); the W factors exp(2 pi i ky' y / N)
+// (argument reduced exactly in integers) go through LDS, thread k <= K sums
+// B(k) and B(-k) in a fixed order
+__global__ __launch_bounds__(64) void low_mode_rows_kernel(const double2 *__restrict__ C, double2 *__restrict__ G,
+                                                           LowModeArgs a) {
+    __shared__ double2 e[64];
+    const int W = 2 * a.K + 1;
+    const int y = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+    if (t < W) {
+        int64_t m = ((int64_t)(t - a.K) * y) % a.N;
+        if (m < 0) m += a.N;
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)a.N, &sn, &cs);
+        e[t] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    if (t > a.K) return;
+    const double2 *Cb = C + (int64_t)b * W * W;
+    auto B = [&](int fx) {
+        const double2 *row = Cb + (int64_t)(fx + a.K) * W;
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < W; ++j) {
+            const double2 c = row[j], w = e[j];
+            re = fma(c.x, w.x, fma(-c.y, w.y, re));
+            im = fma(c.x, w.y, fma(c.y, w.x, im));
+        }
+        return make_double2(re, im);
+    };
+    constexpr double kSqrt2 = 1.41421356237309504880;
+    const double2 bp = B(t);
+    double2 g = bp;
+    if (t > 0) {
+        const double2 bm = B(-t);
+        g = make_double2(bp.x + bm.x, bp.y - bm.y);
+    }
+    G[((int64_t)b * a.N + y) * (a.K + 1) + t] = make_double2(kSqrt2 * g.x, kSqrt2 * g.y);
+}
+
+hipError_t launch_low_modes(void *C, void *G, int N, int K, int nbatch, uint32_t r0, uint32_t seed_lo,
+                            uint32_t seed_hi, double amp0, double neg_beta_4, hipStream_t stream) {
+    if (K < 0 || 2 * K + 1 > 64 || K >= N / 2 || nbatch < 1) return hipErrorInvalidValue;
+    const int W = 2 * K + 1;
+    for (int b0 = 0; b0 < nbatch; b0 += 65535) {
+        const int nb = nbatch - b0 < 65535 ? nbatch - b0 : 65535;
+        LowModeArgs a{N, K, r0 + (uint32_t)b0, seed_lo, seed_hi, amp0, neg_beta_4};
+        double2 *Cb = static_cast<double2 *>(C) + (int64_t)b0 * W * W;
+        double2 *Gb = static_cast<double2 *>(G) + (int64_t)b0 * N * (K + 1);
+        hipLaunchKernelGGL(low_mode_coeff_kernel, dim3(W, nb), dim3(64), 0, stream, Cb, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(low_mode_rows_kernel, dim3(N, nb), dim3(64), 0, stream, Cb, Gb, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // ---------------------------------------------------------------- chirp
 struct ChirpArgs {
     double a[64];

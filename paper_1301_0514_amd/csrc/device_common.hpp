@@ -234,4 +234,28 @@ __device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
+// Random phase spectrum coefficient in FP64 at Fourier pixel (kx, ky) (FFT
+// indices in [0, N)) of realisation r (Sect. 3.1, Eqs. spectre and
+// densite): two 53-bit uniforms from one Philox block, Box-Muller, times
+// amp0 |k'|^(-beta/2) / sqrt(2), with amp0 = sqrt(C_beta R^(2-beta))
+// N^(beta/2) / N; zero at k = 0.
+__device__ __forceinline__ double2 spectrum_coeff_f64(int kx, int ky, int N, uint32_t r, uint32_t seed_lo,
+                                                      uint32_t seed_hi, double amp0, double neg_beta_4) {
+    const U32x4 w = philox4x32_10(U32x4{(uint32_t)kx, (uint32_t)ky, r, 0u}, seed_lo, seed_hi);
+    const uint64_t a = ((uint64_t)w.x0 << 32) | w.x1;
+    const uint64_t b = ((uint64_t)w.x2 << 32) | w.x3;
+    const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * (u2 - rint(u2)), &sn, &cs);
+    const int fx = kx < N / 2 ? kx : kx - N;
+    const int fy = ky < N / 2 ? ky : ky - N;
+    const double k2 = (double)fx * fx + (double)fy * fy;
+    if (k2 == 0.0) return make_double2(0.0, 0.0);
+    const double amp = amp0 * pow(k2, neg_beta_4) * 0.70710678118654752440;
+    return make_double2(amp * rad * cs, amp * rad * sn);
+}
+
+
 }  // namespace scint

@@ -331,7 +331,9 @@ __device__ __forceinline__ cpx<float> spectrum_coeff<float>(int kx, int ky, int 
     const int fx = kx < N / 2 ? kx : kx - N;
     const int fy = ky < N / 2 ? ky : ky - N;
     const uint32_t k2 = (uint32_t)(fx * fx) + (uint32_t)(fy * fy);
-    if (k2 == 0u) return {0.0f, 0.0f};
+    // DC, and the lowest modes when the screen pass adds them in FP64
+    const int K = p.low_k;
+    if (k2 == 0u || (abs(fx) <= K && abs(fy) <= K)) return {0.0f, 0.0f};
     // amp = amp0 k2^(-beta/4): log2 of the mantissa in FP32, the product with
     // -beta/4 in FP64, exp2 of the fractional part in FP32.
     int ex;
@@ -345,20 +347,8 @@ __device__ __forceinline__ cpx<float> spectrum_coeff<float>(int kx, int ky, int 
 template <>
 __device__ __forceinline__ cpx<double> spectrum_coeff<double>(int kx, int ky, int N, uint32_t r,
                                                               const RowProgram &p) {
-    const U32x4 w = philox4x32_10(U32x4{(uint32_t)kx, (uint32_t)ky, r, 0u}, p.seed_lo, p.seed_hi);
-    const uint64_t a = ((uint64_t)w.x0 << 32) | w.x1;
-    const uint64_t b = ((uint64_t)w.x2 << 32) | w.x3;
-    const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
-    const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
-    const double rad = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    sincospi(2.0 * (u2 - rint(u2)), &sn, &cs);
-    const int fx = kx < N / 2 ? kx : kx - N;
-    const int fy = ky < N / 2 ? ky : ky - N;
-    const double k2 = (double)fx * fx + (double)fy * fy;
-    if (k2 == 0.0) return {0.0, 0.0};
-    const double amp = p.amp0 * pow(k2, p.neg_beta_4) * 0.70710678118654752440;
-    return {amp * rad * cs, amp * rad * sn};
+    const double2 c = spectrum_coeff_f64(kx, ky, N, r, p.seed_lo, p.seed_hi, p.amp0, p.neg_beta_4);
+    return {c.x, c.y};
 }
 
 template <typename Real> __device__ __forceinline__ Real sqrt2_of() { return (Real)1.41421356237309504880; }
@@ -395,6 +385,75 @@ template <typename Real, int L, int V> struct RowState {
     int t, tid, g, batch, row, it, it0, it1;  // it0, it1: this workgroup's range of loop iterations
     bool valid;
 };
+
+// FP32 screens, second pass (rows y, after the inverse DFT along x): the
+// screen is sqrt(2) Re v (the high modes, from the FP32 transforms) plus the
+// lowest modes synthesised in FP64,
+//   phi_low(x, y) = Re sum_{k=0}^{K} G_y[k] exp(2 pi i k x / N),
+// G_y (one row of RowProgram::low_tab, K + 1 complex doubles) folding the
+// negative kx' onto the positive ones.  The thread's elements are
+// x = t + m T with T/N = 1/E, so exp(2 pi i k x / N) = W^k c_m^k with
+// W = exp(2 pi i t / N) and c_m^k = exp(2 pi i m k / E) a compile-time
+// constant: the thread forms D[k] = G_y[k] W^k once, and element m is
+// sum_k Re D[k] cos(2 pi m k / E) - Im D[k] sin(2 pi m k / E), the two sums
+// shared with element E - m (same cosines, opposite sines).  The result is
+// kept as the pair v = (hi, lo), hi = phi rounded to FP32 and lo the FP32
+// remainder, so that the stored screen is phi correctly rounded and the phase
+// factor can take phi to FP64 accuracy (RF_HILO).
+template <int L, int V, int E = Plan<L, V>::E>
+__device__ __forceinline__ void add_low_modes(cpx<float> *v, const void *low_tab, int grow, int t) {
+    constexpr int K = low_modes_k_of(L);
+    static_assert(E % 2 == 0, "elements per thread must be even");
+    // the row's coefficients are the same for all its threads: read through
+    // the constant address space, so that a workgroup of one row keeps them
+    // in scalar registers (the table is written by an earlier launch)
+    using ConstRow = const __attribute__((address_space(4))) double *;
+    if constexpr (RowCfg<float, L, V>::B == 1) grow = __builtin_amdgcn_readfirstlane(grow);
+    const ConstRow Gc = (ConstRow)(static_cast<const double *>(low_tab) + (int64_t)grow * (2 * (K + 1)));
+    const double sw = sinpi(2.0 * (double)t / (double)L), cw = cospi(2.0 * (double)t / (double)L);
+    double dr[K + 1], di[K + 1];
+    double pr = 1.0, pim = 0.0;  // W^k
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        const double gr = Gc[2 * k], gi = Gc[2 * k + 1];
+        dr[k] = fma(gr, pr, -gi * pim);
+        di[k] = fma(gr, pim, gi * pr);
+        const double npr = fma(pr, cw, -pim * sw);
+        pim = fma(pr, sw, pim * cw);
+        pr = npr;
+    }
+    constexpr RootTable<E, 1> C{};  // cos, sin of 2 pi e / E
+    constexpr double kSqrt2 = 1.41421356237309504880;
+#pragma unroll
+    for (int m = 0; m <= E / 2; ++m) {
+        double P = 0.0, Q = 0.0;  // sum Re D cos, sum Im D sin
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            // exact 0 and +-1 factors as adds (IEEE forbids folding x * 0)
+            const int e = (m * k) % E;
+            if (e == 0) {
+                P += dr[k];
+            } else if (2 * e == E) {
+                P -= dr[k];
+            } else if (4 * e == E) {
+                Q += di[k];
+            } else if (4 * e == 3 * E) {
+                Q -= di[k];
+            } else {
+                P = fma(dr[k], C.c[e], P);
+                Q = fma(di[k], C.s[e], Q);
+            }
+        }
+        const double phi = fma(kSqrt2, (double)v[m].re, P - Q);
+        const float hi = (float)phi;
+        v[m] = {hi, (float)(phi - (double)hi)};
+        if (m != 0 && m != E / 2) {
+            const double phi2 = fma(kSqrt2, (double)v[E - m].re, P + Q);
+            const float hi2 = (float)phi2;
+            v[E - m] = {hi2, (float)(phi2 - (double)hi2)};
+        }
+    }
+}
 
 template <typename Real, int L, int V, int CODE>
 __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &op) {
@@ -470,12 +529,24 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = cscale(v[m], sc * src[m * T]);
     } else if constexpr (CODE == ROP_SQRT2RE) {
+        // FP32 screens always take their lowest modes from the FP64 table
+        // (the host builds it for every FP32 screen pass)
+        if constexpr (std::is_same<Real, float>::value) {
+            add_low_modes<L, V>(v, st.prog->low_tab, st.batch * L + st.row, st.t);  // < 2^30 rows
+        } else {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = {sqrt2_of<Real>() * v[m].re, (Real)0};
+            for (int m = 0; m < E; ++m) v[m] = {sqrt2_of<Real>() * v[m].re, (Real)0};
+        }
     } else if constexpr (CODE == ROP_EXP_RE) {
+        // FP32: the phase is the (hi, lo) pair of ROP_SQRT2RE, summed in FP64
         const double sturn = s * (0.5 / kPi);
+        if constexpr (std::is_same<Real, float>::value) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)v[m].re);
+            for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * ((double)v[m].re + (double)v[m].im));
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = expi_turns<Real>(sturn * (double)v[m].re);
+        }
     } else if constexpr (CODE == ROP_MUL_ROWTAB) {
         const cpx<Real> a = static_cast<const cpx<Real> *>(op.ptr)[(int64_t)st.it * op.iter_stride + st.row];
 #pragma unroll

@@ -28,8 +28,9 @@ enum RowOpCode : int32_t {
     ROP_MUL_TAB,     // v *= tab[e]  (complex table along the row; flag 1: conjugate)
     ROP_MUL_RTAB2D,  // v *= tab[row][e]  (real 2-D table, no batch offset)
     ROP_MUL_RLOAD,   // v *= param * src[e]  (real array)
-    ROP_SQRT2RE,     // v = (sqrt(2) Re v, 0)
-    ROP_EXP_RE,      // v = exp(i s Re v)
+    ROP_SQRT2RE,     // v = (sqrt(2) Re v, 0); FP32: v = (hi, lo) of sqrt(2) Re v
+                     //   plus the FP64 low modes of the row (low_tab)
+    ROP_EXP_RE,      // v = exp(i s Re v); FP32: exp(i s (Re v + Im v)), the sum in FP64
     ROP_STORE_C,     // dst[e] = v
     ROP_STORE_R,     // dst[e] = param * Re v
     ROP_ACC_ABS2,    // acc += w |v|^2
@@ -71,6 +72,12 @@ struct RowOp {
 constexpr int kRowMaxOps = 20;
 constexpr int kRowMaxIter = 64;
 
+// Half-width of the square of lowest Fourier modes, |kx'|, |ky'| <= K, that
+// the FP32 screens synthesise in FP64 (the FP32 transforms carry the rest):
+// 16, or N/2 - 1 on grids too small for it (the Nyquist row and column stay
+// with the transforms).
+constexpr int32_t low_modes_k_of(int N) { return N / 2 - 1 < 16 ? N / 2 - 1 : 16; }
+
 // Transposes a row pass carries as extra workgroups of its own launch
 // (programs whose first op is ROP_SIDE_T; complex64 only): units [u0, u1) of
 // the N x N matrices at `in`, written transposed to the same place in `out`.
@@ -107,7 +114,14 @@ struct RowProgram {
     // Only for programs whose iterations are independent; the launcher
     // falls back to 1 where it does not apply (the results are the same).
     int32_t iter_split;
-    int32_t reserved;
+    // FP32 screens: ROP_NOISE leaves out the Fourier modes with |kx'|,
+    // |ky'| <= low_k (low_modes_k_of(N); 0 in every other program and in
+    // FP64), and ROP_SQRT2RE adds them back in FP64 from low_tab, the table
+    // [batch][N][low_modes_k_of(N) + 1] of complex doubles G with
+    // phi_low(x, y) = Re sum_k G[b][y][k] exp(2 pi i k x / N) (required by
+    // every FP32 program that contains ROP_SQRT2RE).
+    int32_t low_k;
+    const void *low_tab;
 };
 
 // Feature sets: which register arrays beyond the row itself a kernel keeps.

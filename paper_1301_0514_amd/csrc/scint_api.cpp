@@ -614,16 +614,45 @@ static std::vector<double> weight_amps(const std::vector<double> &w, size_t j0, 
 double f_beta(double beta) { return std::pow(2.0, -beta) * beta * std::tgamma(-beta / 2.0) / std::tgamma(beta / 2.0); }
 
 // Fills the noise operands: amp0 = sqrt(C_beta R^(2-beta)) N^(beta/2) / N.
-void set_noise(RowProgram &p, int N, double R, double beta, uint64_t seed, uint32_t r0) {
+// FP32 screens leave the lowest modes to the FP64 synthesis (low_k).
+void set_noise(RowProgram &p, int N, double R, double beta, uint64_t seed, uint32_t r0, int dtype) {
     const double c_beta = 1.0 / (2.0 * std::pow(2.0 * kPiD, beta - 1.0) * f_beta(beta));
     p.amp0 = std::sqrt(c_beta * std::pow(R, 2.0 - beta)) * std::pow((double)N, beta / 2.0) / (double)N;
     p.neg_beta_4 = -beta / 4.0;
     p.seed_lo = (uint32_t)(seed & 0xFFFFFFFFull);
     p.seed_hi = (uint32_t)(seed >> 32);
     p.r0 = (int32_t)r0;
+    p.low_k = dtype == PS_F32 ? low_modes_k_of(N) : 0;
 }
 
 int64_t nn(int N) { return (int64_t)N * N; }
+
+// Workspace of the FP64 low-mode tables of nb FP32 screens (0 for FP64).
+size_t low_mode_bytes(int N, int nb, int dtype) {
+    if (dtype != PS_F32) return 0;
+    const size_t K = (size_t)low_modes_k_of(N), W = 2 * K + 1;
+    return (size_t)nb * ((size_t)N * (K + 1) + W * W) * 16 + 512;
+}
+
+// The FP64 low modes of FP32 screens r0 .. r0 + nb - 1 (Sect. 3.1): the FP32
+// transforms carry the Fourier modes outside the square |kx'|, |ky'| <= K,
+// and the second screen pass adds the square's part, summed in FP64 from the
+// row table built here at `tab` (low_mode_bytes of workspace), to the
+// screen.  Sets p.low_k and p.low_tab of that pass (nothing for FP64).
+int low_mode_pass(RowProgram &p, int N, double R, double beta, uint64_t seed, uint32_t r0, int nb, int dtype,
+                  void *tab, hipStream_t stream) {
+    if (dtype != PS_F32) return PS_OK;
+    RowProgram q;
+    std::memset(&q, 0, sizeof(q));
+    set_noise(q, N, R, beta, seed, r0, dtype);
+    const int K = q.low_k;
+    char *G = static_cast<char *>(tab);
+    char *C = G + (size_t)nb * N * (K + 1) * 16;
+    HIP_TRY(launch_low_modes(C, G, N, K, nb, r0, q.seed_lo, q.seed_hi, q.amp0, q.neg_beta_4, stream));
+    p.low_k = K;
+    p.low_tab = G;
+    return PS_OK;
+}
 
 // Upper bound on workspace bytes a call plans for (whole-batch processing is
 // split into chunks above it): half the free device memory at the first call
@@ -715,7 +744,7 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
     for (int k = 0; k < J; ++k) {
         const int j0 = (int)((int64_t)nb * k / J), jn = (int)((int64_t)nb * (k + 1) / J) - j0;
         ProgBuilder a(N, (int64_t)jn * N);
-        set_noise(a.p, N, R, beta, seed, r0 + (uint32_t)j0);
+        set_noise(a.p, N, R, beta, seed, r0 + (uint32_t)j0, dtype);
         if (k > 0) a.op(ROP_SIDE_T);
         a.op(ROP_NOISE).op(ROP_FFT_INV).op(ROP_STORE_C, static_cast<char *>(W1) + j0 * cbytes, nn(N), N);
         if (k == 0) {
@@ -889,16 +918,17 @@ int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed, 
     const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
     for (int b0 = 0; b0 < n_real; b0 += nb_max) {
         const int nb = std::min(nb_max, n_real - b0);
+        const uint32_t r0 = first_realisation + (uint32_t)b0;
         void *ws = nullptr;
-        if (int rc = get_workspace(stream, 2 * cbytes * nb + 512, &ws)) return rc;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + low_mode_bytes(N, nb, dtype) + 1024, &ws)) return rc;
         Carver c;
         char *base = static_cast<char *>(ws);
         void *W1 = base + c.take(cbytes * nb);
         void *W2 = base + c.take(cbytes * nb);
-        if (int rc = screen_passes(N, r_diff / delta, beta, seed, first_realisation + (uint32_t)b0, nb, dtype, W1,
-                                   W2, stream))
-            return rc;
+        void *LT = base + c.take(low_mode_bytes(N, nb, dtype));
+        if (int rc = screen_passes(N, r_diff / delta, beta, seed, r0, nb, dtype, W1, W2, stream)) return rc;
         ProgBuilder b(N, (int64_t)nb * N);
+        if (int rc = low_mode_pass(b.p, N, r_diff / delta, beta, seed, r0, nb, dtype, LT, stream)) return rc;
         char *phi = static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
         b.op(ROP_LOAD_C, W2, nn(N), N).op(ROP_FFT_INV).op(ROP_SQRT2RE).op(ROP_STORE_R, phi, nn(N), N, 0, 0, 1.0);
         if (int rc = run_row<ProgScreenTag>(dtype, N, b.p, b.n, stream)) return rc;
@@ -926,19 +956,21 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
     const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
     for (int b0 = 0; b0 < n_real; b0 += nb_max) {
         const int nb = std::min(nb_max, n_real - b0);
+        const uint32_t r0 = first_realisation + (uint32_t)b0;
         void *ws = nullptr;
-        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + low_mode_bytes(N, nb, dtype) + 1536, &ws))
+            return rc;
         Carver c;
         char *base = static_cast<char *>(ws);
         void *W1 = base + c.take(cbytes * nb);
         void *W2 = base + c.take(cbytes * nb);
         void *H = base + c.take(tbytes);
+        void *LT = base + c.take(low_mode_bytes(N, nb, dtype));
         if (int rc = chirp_tables(H, N, {rho}, dtype, true, stream)) return rc;
-        if (int rc = screen_passes(N, r_diff / delta, beta, seed, first_realisation + (uint32_t)b0, nb, dtype, W1,
-                                   W2, stream))
-            return rc;
+        if (int rc = screen_passes(N, r_diff / delta, beta, seed, r0, nb, dtype, W1, W2, stream)) return rc;
         char *phi = phi_out ? static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype) : nullptr;
         ProgBuilder b(N, (int64_t)nb * N);
+        if (int rc = low_mode_pass(b.p, N, r_diff / delta, beta, seed, r0, nb, dtype, LT, stream)) return rc;
         b.op(ROP_LOAD_C, W2, nn(N), N)
             .op(ROP_FFT_INV)
             .op(ROP_SQRT2RE)

@@ -73,14 +73,25 @@ def test_single_4096(S, P, oracle, R, seed):
 
 
 # ------------------------------------------------------------ paper-scale grids
-@pytest.mark.parametrize("N,beta", [(10000, 11 / 3), (10000, 3.9), (16384, 11 / 3)])
+@pytest.mark.parametrize("N", [10000, 16384])
+@pytest.mark.parametrize("beta", [3.1, 3.2, 11 / 3, 3.9])
 def test_paper_scale_vs_oracle(S, P, oracle, N, beta):
+    """Every (N, beta) of the paper-scale workload (Eq. spectre's exponent:
+    3.2 and 3.9, Kolmogorov 11/3, and the paper's 3.1 of Sect. 5), screen and
+    pattern against the FP64 oracle at every pixel."""
     c = [x for x in P.PAPER_SCALE if x.N == N and abs(x.beta - beta) < 1e-9][0]
-    I = S.ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, c.lam, c.z)
-    I = host(I)[0]
-    I_ref = oracle.propagate(oracle.screen(c.N, c.R, c.beta, 1, 0), c.rho)
+    I, phi = S.ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, c.lam, c.z, want_phi=True)
+    I, phi = host(I)[0], host(phi)[0]
+    phi_ref = oracle.screen(c.N, c.R, c.beta, 1, 0)
+    d = phi - phi_ref
+    phi_rms = float(np.sqrt(np.mean(phi_ref * phi_ref)))
+    phi_err = float(np.sqrt(np.mean(d * d)))
+    del phi, d
+    I_ref = oracle.propagate(phi_ref, c.rho)
     e_rms, e_max = errs(I, I_ref)
-    print("N=%d beta=%.3f e_rms=%.2e e_max=%.2e" % (N, beta, e_rms, e_max))
+    print("N=%d beta=%.3f phi_rms=%.1f rad phi err %.1e rel, I e_rms=%.2e e_max=%.2e" % (
+        N, beta, phi_rms, phi_err / phi_rms, e_rms, e_max))
+    assert phi_err < 2e-7 * phi_rms
     assert e_rms < F32_RMS and e_max < F32_MAX
 
 
@@ -318,27 +329,25 @@ def test_separable_screens_every_pixel(S, oracle, N):
 def test_largest_sizes_screen_fresnel_vs_oracle(S, oracle, N):
     """Screen generation and propagation at the sizes whose rows nearly fill
     the LDS, against the FP64 oracle at every pixel (R_diff = 4.42 px,
-    R_F = 57.5 px: the paper's 20000^2 configuration).
-
-    With R_diff = 4.42 px the Kolmogorov phase reaches several hundred
-    radians.  The FP32 screen carries about 2^-24 |phi| of rounding per pixel
-    (storage and the inverse FFT), a white phase error that the unitary
-    propagation turns into an intensity error of about twice its size (mean
-    intensity 1).  The RMS bar is therefore max(2e-5, 8 2^-24 phi_rms); the
-    max bar stays at 1e-3."""
+    R_F = 57.5 px: the paper's 20000^2 configuration, Sect. 3.1 and Fig.
+    pattern).  The Kolmogorov phase reaches several hundred radians here;
+    its lowest modes, which carry most of it, are synthesised in FP64, so
+    the FP32 transforms only round the weak high modes and the pattern meets
+    the same bar as every other configuration."""
     rho, R, lam = 57.5, 4.42, 2.162e-6
     z = 2 * np.pi * rho ** 2 / lam
     I, phi = S.ps_screen_fresnel(N, 1.0, R, 11 / 3, 5, lam, z, want_phi=True)
     phi_ref = oracle.screen(N, R, 11 / 3, 5, 0)
     phi_rms = float(np.sqrt(np.mean(phi_ref * phi_ref)))
     d = host(phi)[0] - phi_ref
-    assert np.sqrt(np.mean(d * d)) < 3e-6 * phi_rms
+    phi_err = float(np.sqrt(np.mean(d * d)))
     del phi, d
     I_ref = oracle.propagate(phi_ref, rho)
     e_rms, e_max = errs(host(I)[0], I_ref)
-    bar = max(F32_RMS, 8 * 2.0 ** -24 * phi_rms)
-    print("N=%d phi_rms=%.1f rad e_rms=%.2e (bar %.2e) e_max=%.2e" % (N, phi_rms, e_rms, bar, e_max))
-    assert e_rms < bar and e_max < F32_MAX
+    print("N=%d phi_rms=%.1f rad phi err %.1e rel, I e_rms=%.2e e_max=%.2e" % (
+        N, phi_rms, phi_err / phi_rms, e_rms, e_max))
+    assert phi_err < 2e-7 * phi_rms
+    assert e_rms < F32_RMS and e_max < F32_MAX
 
 
 def test_paper_ks_band_20000(S, P):

@@ -72,11 +72,14 @@ SIZES = [16, 40, 64, 100, 256, 1000, 1024]
 @pytest.mark.parametrize("N,R,beta", [(16, 2.0, 11 / 3), (40, 3.0, 3.2), (64, 4.0, 11 / 3), (100, 5.0, 3.9),
                                       (256, 4.0, 11 / 3), (1000, 8.0, 3.1), (2048, 24.0, 11 / 3)])
 def test_screen(S, oracle, dtype, N, R, beta):
+    # FP32 screens carry the lowest modes (|kx'|, |ky'| <= 16) in FP64 and
+    # the rest through the FP32 transforms, so the stored screen is within a
+    # few rounding units of FP32 of the exact one
     seed, r0, n = 17, 3, 2
     phi = host(S.ps_generate(N, 1.0, R, beta, seed, r0, n, dtype))
     for b in range(n):
         ref = oracle.screen(N, R, beta, seed, r0 + b)
-        check_field(phi[b], ref, dtype)
+        check_field(phi[b], ref, dtype, rms_tol=2e-7)
 
 
 def test_screen_seed_high_word(S, oracle):
