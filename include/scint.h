@@ -131,6 +131,28 @@ int fresnel_propagate(int N, double delta, double lambda, double z, const void *
                       double phase_scale, int n, int dtype, void *I_out, void *hip_stream);
 
 /*
+ * fresnel_propagate_noalloc -- fresnel_propagate for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, result and errors as
+ * fresnel_propagate, computed by the same kernels in the plain order (x pass,
+ * transpose, y pass, transpose) with FFT plan 0 and its twiddle table built on
+ * the device, so FP32 results agree with fresnel_propagate to FP32 rounding.
+ * Its intermediates live in one static device array per GPU of 65 MiB
+ * (68157440 bytes), held from the library's load until the process ends; a
+ * call needs 16 N^2 n bytes (FP32; 32 N^2 n in FP64) plus its tables there
+ * and returns PS_E_SIZE, writing nothing, when that exceeds the array (FP32:
+ * up to n = 1 at N = 2048, n = 4 at 1024; FP64: n = 2 at 1024).  The call
+ * enqueues kernels only: no hipMalloc, hipFree, host copy or
+ * synchronisation, no plan tuning and no cached tables; the first call on a
+ * device resolves the array's device address (hipGetSymbolAddress).  Every
+ * call on one GPU uses the same array: calls that overlap in time on one GPU
+ * (on different streams, or from several threads) race and corrupt each
+ * other's results, so serialise them, e.g. on one stream.
+ */
+int fresnel_propagate_noalloc(int N, double delta, double lambda, double z, const void *phi,
+                              double phase_scale, int n, int dtype, void *I_out, void *hip_stream);
+
+/*
  * ps_screen_fresnel -- ps_generate followed by fresnel_propagate with s = 1,
  * fused so that the screen need not go through device memory.
  *   phi_out   optional device [n_real][N][N] real copy of the screen, or NULL

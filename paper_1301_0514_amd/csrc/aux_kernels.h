@@ -18,6 +18,13 @@ hipError_t launch_transpose(const void *in, void *out, int N, int64_t nbatch, in
 hipError_t launch_chirp_tables(void *tab, int N, const double *a, int n, double scale, bool f64,
                                hipStream_t stream, const double *amp = nullptr);
 
+// The twiddle table of an FFT plan built on the device: entry off[s] + k R[s]
+// + r = exp(-2 pi i r k / (ns[s] R[s])) for the stages described (n <= 8,
+// `total` entries), the product r k reduced modulo ns R in integers and the
+// sine/cosine taken in FP64, rounded once to the working precision.
+hipError_t launch_twiddle_table(void *tab, int n_stages, const int *ns, const int *R, const int *off, int total,
+                                bool f64, hipStream_t stream);
+
 // img[y][x] = value if dx^2 + dy^2 <= r2 (minimum-image offsets of pixel
 // (x, y) from the origin), else 0.
 hipError_t launch_disk_image(void *img, int N, double r2, double value, bool f64, hipStream_t stream);

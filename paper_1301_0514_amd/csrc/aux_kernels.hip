@@ -154,6 +154,47 @@ hipError_t launch_low_modes(void *C, void *G, int N, int K, int nbatch, uint32_t
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------- twiddles
+struct TwiddleArgs {
+    int n, total;
+    int ns[8], R[8], off[8];
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void twiddle_table_kernel(cpx<Real> *tab, TwiddleArgs a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.total) return;
+    int s = 0;
+    while (s + 1 < a.n && i >= a.off[s + 1]) ++s;
+    const int j = i - a.off[s];
+    const int64_t k = j / a.R[s], r = j - k * a.R[s];
+    const int64_t M = (int64_t)a.ns[s] * a.R[s];
+    const int64_t m = (r * k) % M;
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)M, &sn, &cs);
+    tab[i] = {(Real)cs, (Real)(-sn)};
+}
+
+hipError_t launch_twiddle_table(void *tab, int n_stages, const int *ns, const int *R, const int *off, int total,
+                                bool f64, hipStream_t stream) {
+    if (n_stages < 0 || n_stages > 8 || total < 0) return hipErrorInvalidValue;
+    if (total == 0) return hipSuccess;
+    TwiddleArgs a{};
+    a.n = n_stages;
+    a.total = total;
+    for (int s = 0; s < n_stages; ++s) {
+        a.ns[s] = ns[s];
+        a.R[s] = R[s];
+        a.off[s] = off[s];
+    }
+    const dim3 grid((total + 255) / 256);
+    if (f64)
+        hipLaunchKernelGGL((twiddle_table_kernel<double>), grid, dim3(256), 0, stream, static_cast<cpx<double> *>(tab), a);
+    else
+        hipLaunchKernelGGL((twiddle_table_kernel<float>), grid, dim3(256), 0, stream, static_cast<cpx<float> *>(tab), a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- chirp
 struct ChirpArgs {
     double a[64];

@@ -42,4 +42,14 @@ hipError_t launch_row(int L, int V, const RowProgram &prog, const void *tw, hipS
 int twiddle_entries(int L, int V);
 bool build_twiddles(int L, int V, double *out_ri /* 2 * twiddle_entries(L, V) */);
 
+// The same tables described by their stages (for a device-side build): for
+// each stage s >= 1 of plan (L, V), the span ns of the earlier stages, its
+// radix R and the offset of its ns R entries; total entries in `total`.
+struct TwiddleStages {
+    int n;
+    int ns[8], R[8], off[8];
+    int total;
+};
+bool twiddle_stages(int L, int V, TwiddleStages *d);
+
 }  // namespace scint

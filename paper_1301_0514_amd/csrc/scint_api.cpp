@@ -31,6 +31,13 @@
 
 using namespace scint;
 
+// Device memory of fresnel_propagate_noalloc: one array per GPU, held from the
+// library's load until the process ends, shared by every call on that GPU.
+// Host code uses it only through the address hipGetSymbolAddress returns for
+// the current device (g_scratch below), never through this name.
+constexpr size_t kNoAllocScratchBytes = (size_t)65 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -766,6 +773,38 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
                      2 * (int)real_bytes(dtype), stream);
 }
 
+// ------------------------------------------------------------ no-allocation path
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices];  // device address of `scratch` per GPU, set on first use
+
+// The scratch array's device address on the current GPU: looked up once per
+// device (the first call there), then read from g_scratch.
+int noalloc_scratch(void **out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return fail(PS_E_DEVICE, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PS_E_DEVICE, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return PS_OK;
+}
+
+// Row pass with plan 0 and a given twiddle table: kernels only (no tuning,
+// no table cache, no timing events).
+template <class Tag> int launch_row_plan0(int dtype, int N, const RowProgram &p, const void *tw, hipStream_t stream) {
+    const hipError_t e = dtype == PS_F64 ? launch_row<double, Tag>(N, 0, p, tw, stream)
+                                         : launch_row<float, Tag>(N, 0, p, tw, stream);
+    if (e != hipSuccess) return fail(PS_E_DEVICE, std::string("row pass launch: ") + hipGetErrorString(e));
+    return PS_OK;
+}
+
 }  // namespace
 
 // ============================================================ C ABI
@@ -1212,6 +1251,66 @@ int fresnel_propagate(int N, double delta, double lambda, double z, const void *
         char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
         if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
     }
+    return PS_OK;
+}
+
+int fresnel_propagate_noalloc(int N, double delta, double lambda, double z, const void *phi, double phase_scale,
+                              int n, int dtype, void *I_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !I_out) return fail(PS_E_NULL, "phi and I_out must be non-NULL");
+    if (int rc = check_aligned({phi, I_out})) return rc;
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    const size_t rb = real_bytes(dtype), cb = 2 * rb;
+    const size_t rbytes = (size_t)nn(N) * rb * n;
+    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
+    TwiddleStages ts;
+    if (!twiddle_stages(N, 0, &ts)) return fail(PS_E_SIZE, "no FFT plan for this size");
+    // scratch: two complex fields per screen, the chirp table, the twiddles
+    Carver c;
+    const size_t oW1 = c.take(cb * (size_t)nn(N) * n), oW2 = c.take(cb * (size_t)nn(N) * n);
+    const size_t oH = c.take(cb * (size_t)N), oT = c.take(cb * (size_t)std::max(ts.total, 1));
+    if (c.used > kNoAllocScratchBytes)
+        return fail(PS_E_SIZE, "fresnel_propagate_noalloc needs " + std::to_string(c.used) +
+                                   " bytes of scratch for this size and batch, more than its " +
+                                   std::to_string(kNoAllocScratchBytes) + "-byte array (4 N^2 n real elements "
+                                   "plus tables); use fresnel_propagate");
+    void *scr = nullptr;
+    if (int rc = noalloc_scratch(&scr)) return rc;
+    char *base = static_cast<char *>(scr);
+    char *W1 = base + oW1, *W2 = base + oW2, *H = base + oH, *TW = base + oT;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const bool f64 = dtype == PS_F64;
+    HIP_TRY(launch_twiddle_table(TW, ts.n, ts.ns, ts.R, ts.off, ts.total, f64, stream));
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const double a = kPiD * rho * rho / ((double)N * (double)N);
+    HIP_TRY(launch_chirp_tables(H, N, &a, 1, 1.0 / N, f64, stream));
+    // x pass: exp(i s phi), DFT, chirp, inverse DFT; transpose; y pass:
+    // DFT, chirp, inverse DFT, |.|^2 (into W1, transposed); transpose to I_out
+    ProgBuilder x(N, (int64_t)n * N);
+    x.op(ROP_LOOP)
+        .op(ROP_LOAD_PHASE, phi, nn(N), N, 0, 0, phase_scale)
+        .op(ROP_FFT_FWD)
+        .op(ROP_MUL_TAB, H)
+        .op(ROP_FFT_INV)
+        .op(ROP_STORE_C, W1, nn(N), N)
+        .op(ROP_ENDLOOP);
+    if (int rc = launch_row_plan0<ProgPhasePropTag>(dtype, N, x.p, TW, stream)) return rc;
+    HIP_TRY(launch_transpose(W1, W2, N, n, (int)cb, stream));
+    ProgBuilder y(N, (int64_t)n * N);
+    y.op(ROP_LOOP)
+        .op(ROP_LOAD_C, W2, nn(N), N)
+        .op(ROP_FFT_FWD)
+        .op(ROP_MUL_TAB, H)
+        .op(ROP_FFT_INV)
+        .op(ROP_ACC_ABS2U)
+        .op(ROP_ENDLOOP)
+        .op(ROP_STORE_ACC, W1, nn(N), N);
+    if (int rc = launch_row_plan0<ProgPropIntensityTag>(dtype, N, y.p, TW, stream)) return rc;
+    HIP_TRY(launch_transpose(W1, I_out, N, n, (int)rb, stream));
     return PS_OK;
 }
 

@@ -80,6 +80,44 @@ int twiddle_entries(int L, int V) {
 #undef SCINT_CASE
 }
 
+template <int L, int V> static int stages(TwiddleStages *d) {
+    using P = Plan<L, V>;
+    d->n = 0;
+    int ns = 1;
+    for (int st = 0; st < P::NS; ++st) {
+        if (st > 0) {
+            d->ns[d->n] = ns;
+            d->R[d->n] = P::R[st];
+            d->off[d->n] = twiddle_offset<L, V>(st);
+            ++d->n;
+        }
+        ns *= P::R[st];
+    }
+    d->total = twiddle_count<L, V>();
+    return d->n;
+}
+
+bool twiddle_stages(int L, int V, TwiddleStages *d) {
+#define SCINT_VCASE(LL, VV)                  \
+    if (L == LL && V == VV) {                \
+        stages<LL, VV>(d);                   \
+        return true;                         \
+    }
+    SCINT_VARIANTS_F32(SCINT_VCASE)
+#undef SCINT_VCASE
+    if (V != 0) return false;
+#define SCINT_CASE(LL)      \
+    case LL:                \
+        stages<LL, 0>(d);   \
+        return true;
+    switch (L) {
+        SCINT_SIZES_F32(SCINT_CASE)
+    default:
+        return false;
+    }
+#undef SCINT_CASE
+}
+
 bool build_twiddles(int L, int V, double *out) {
 #define SCINT_VCASE(LL, VV)     \
     if (L == LL && V == VV) {   \

@@ -35,6 +35,8 @@ SIGNATURES = {
     "ps_supported_size_at": (_c_int, [_c_int, _c_int]),
     "ps_generate": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _c_u64, _c_u32, _c_int, _c_int, _vp, _vp]),
     "fresnel_propagate": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_int, _c_int, _vp, _vp]),
+    "fresnel_propagate_noalloc": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_int, _c_int, _vp,
+                                           _vp]),
     "ps_screen_fresnel": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _c_u64, _c_u32, _c_int, _c_dbl, _c_dbl,
                                    _c_int, _vp, _vp, _vp]),
     "illumination_polychromatic": (_c_int, [_c_int, _c_dbl, _c_dbl, _vp, _c_dbl, _dp, _dp, _c_int, _c_int,
@@ -278,6 +280,24 @@ def fresnel_propagate(phi: torch.Tensor, delta, lam, z, phase_scale=1.0,
                                           float(phase_scale), n, _dtype_code(phi.dtype), _ptr(out),
                                           _stream(phi.device))
     _check("fresnel_propagate", rc)
+    return out
+
+
+def fresnel_propagate_noalloc(phi: torch.Tensor, delta, lam, z, phase_scale=1.0,
+                              out: torch.Tensor | None = None) -> torch.Tensor:
+    """fresnel_propagate through the entry point that allocates no device
+    memory (its intermediates live in the library's fixed scratch array);
+    see scint.h.  With `out` given, the call itself allocates nothing."""
+    N = phi.shape[-1]
+    n = _batch_of(phi, N)
+    if out is None:
+        out = torch.empty_like(phi)
+    else:
+        _check_like("out", out, phi.shape, phi.dtype, phi.device)
+    rc = load_library().fresnel_propagate_noalloc(int(N), float(delta), float(lam), float(z), _ptr(phi),
+                                                  float(phase_scale), n, _dtype_code(phi.dtype), _ptr(out),
+                                                  _stream(phi.device))
+    _check("fresnel_propagate_noalloc", rc)
     return out
 
 
