@@ -445,7 +445,7 @@ def main(argv=None) -> int:
                 for s in c.seeds:
                     r = scint.load_library().ps_screen_fresnel(
                         c.N, 1.0, c.R, c.beta, s, 0, 1, c.lam, c.z, 0, None,
-                        scint._ptr(Iout), scint._stream(dev))
+                        scint._ptr(Iout), None, scint._stream(dev))
                     if r != 0:
                         raise RuntimeError("ps_screen_fresnel failed %d" % r)
 
@@ -461,7 +461,7 @@ def main(argv=None) -> int:
 
             def paper():
                 r = scint.load_library().ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, 0, 1, c.lam, c.z, 0, None,
-                                                            scint._ptr(out_t), scint._stream(dev))
+                                                            scint._ptr(out_t), None, scint._stream(dev))
                 if r != 0:
                     raise RuntimeError("ps_screen_fresnel failed %d" % r)
 
@@ -535,7 +535,8 @@ def main(argv=None) -> int:
         log("K_s band 20000^2 x 21 lambda: %.1f ms, m = %.3f" % (tk, sec["paper_ks_20000_21_lambda"]["m"]))
         del phik, Ik
 
-        # forward + adjoint, 16 x 2048^2
+        # forward + adjoint, 16 x 2048^2: the forward keeps the field as the
+        # adjoint's checkpoint; the recomputing adjoint is timed beside it
         g = presets.GRAD_2048
         nr = presets.GRAD_N_REAL
         It = torch.empty((nr, g.N, g.N), dtype=torch.float32, device=dev)
@@ -544,20 +545,28 @@ def main(argv=None) -> int:
         gphi = torch.empty_like(It)
         Igr = torch.empty_like(It)
         phig = torch.empty_like(It)
+        fieldg = torch.empty((nr, g.N, g.N, 2), dtype=torch.float32, device=dev)
 
-        def fwd_adj():
+        def fwd_adj(checkpoint):
             lib = scint.load_library()
             st = scint._stream(dev)
             r = lib.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, 1, 0, nr, g.lam, g.z, 0, scint._ptr(phig),
-                                      scint._ptr(Igr), st)
-            _, gI = scint.ps_l2_loss(Igr, It)
-            scint.fresnel_propagate_vjp(phig, 1.0, g.lam, g.z, gI, 1.0, out=gphi)
+                                      scint._ptr(Igr), scint._ptr(fieldg) if checkpoint else None, st)
             if r != 0:
                 raise RuntimeError("ps_screen_fresnel failed %d" % r)
+            _, gI = scint.ps_l2_loss(Igr, It)
+            scint.fresnel_propagate_vjp(phig, 1.0, g.lam, g.z, gI, 1.0, out=gphi,
+                                        field=fieldg if checkpoint else None)
 
-        tg = timed(fwd_adj, 3)
-        sec["grad_2048x16_forward_adjoint"] = {"ms_per_step": tg, "pt_per_s": nr * g.N ** 2 / (tg / 1e3)}
-        log("16 x 2048^2 forward+adjoint: %.3f ms" % tg)
+        tg = timed(lambda: fwd_adj(True), 3)
+        tr = timed(lambda: fwd_adj(False), 3)
+        # survey model: forward 44 B/pt (screen, field and pattern kept) +
+        # adjoint 36 B/pt
+        sec["grad_2048x16_forward_adjoint"] = {"ms_per_step": tg, "pt_per_s": nr * g.N ** 2 / (tg / 1e3),
+                                               "ms_per_step_recomputing_adjoint": tr,
+                                               "frac_of_hbm_roofline_80B_per_pt":
+                                                   80.0 * nr * g.N ** 2 / (tg / 1e3) / (HBM_PEAK_GBS * 1e9)}
+        log("16 x 2048^2 forward+adjoint: %.3f ms with the checkpoint, %.3f ms recomputing" % (tg, tr))
         out["secondary"] = sec
 
     print(json.dumps(out), flush=True)

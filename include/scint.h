@@ -153,14 +153,34 @@ int fresnel_propagate_noalloc(int N, double delta, double lambda, double z, cons
                               double phase_scale, int n, int dtype, void *I_out, void *hip_stream);
 
 /*
+ * fresnel_propagate_field -- fresnel_propagate that also keeps the complex
+ * field A = N^-2 IDFT[H DFT[U]] of each screen as the checkpoint of its
+ * adjoint (fresnel_propagate_vjp's `field`), in the layout of the second
+ * 1-D pass: field_out[b][x][y] (x slow, y fast; interleaved re, im), so
+ * that I[b][y][x] = |field_out[b][x][y]|^2.  Same kernels and result as the
+ * plain (single-job) order of fresnel_propagate.
+ *   field_out  device [n][N][N] complex (2 n N^2 reals); must not overlap
+ *              phi or I_out (PS_E_ALIAS)
+ */
+int fresnel_propagate_field(int N, double delta, double lambda, double z, const void *phi,
+                            double phase_scale, int n, int dtype, void *I_out, void *field_out,
+                            void *hip_stream);
+
+/*
  * ps_screen_fresnel -- ps_generate followed by fresnel_propagate with s = 1,
  * fused so that the screen need not go through device memory.
- *   phi_out   optional device [n_real][N][N] real copy of the screen, or NULL
- *   I_out     device [n_real][N][N] real
+ *   phi_out    optional device [n_real][N][N] real copy of the screen, or NULL
+ *   I_out      device [n_real][N][N] real
+ *   field_out  optional device [n_real][N][N] complex checkpoint of the field
+ *              for fresnel_propagate_vjp (layout of fresnel_propagate_field),
+ *              or NULL
+ * The FP32 screen's lowest Fourier modes (|kx'|, |ky'| <= 16) are synthesised
+ * in FP64 and the phase of exp(i phi) is formed from the screen to FP64
+ * accuracy; phi_out holds the screen rounded once to FP32.
  */
 int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t seed,
                       uint32_t first_realisation, int n_real, double lambda, double z,
-                      int dtype, void *phi_out, void *I_out, void *hip_stream);
+                      int dtype, void *phi_out, void *I_out, void *field_out, void *hip_stream);
 
 /*
  * illumination_polychromatic -- co-added pattern over a passband
@@ -207,17 +227,23 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
  * product) for a loss L(I) whose gradient dL/dI is grad_I:
  *   g_A = 2 grad_I A;  g_U = N^-2 IDFT[ conj(H) DFT[g_A] ];
  *   dL/dphi = s Im(g_U conj(U)).
- * The forward field A is recomputed from phi (nothing is kept between calls).
+ * The forward field A is taken from the checkpoint `field` when given (four
+ * 1-D FFT passes per point), else recomputed from phi (eight).
  *   phi, grad_I        device [n][N][N] real
- *   grad_phi_out       device [n][N][N] real; must not overlap phi or grad_I
+ *   field              optional device [n][N][N] complex, the checkpoint
+ *                      written by fresnel_propagate_field or
+ *                      ps_screen_fresnel for the same phi, lambda, z and s;
+ *                      NULL to recompute
+ *   grad_phi_out       device [n][N][N] real; must not overlap phi, grad_I or field
  *   phi_dot_grad_out   optional host array of n doubles: sum_m phi dL/dphi
  *                      per screen (FP64), from which
  *                      dL/dlog R_diff = ((2 - beta)/2) phi_dot_grad, since the
  *                      screen scales as R_diff^((2-beta)/2) for fixed noise.
  */
 int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const void *phi,
-                          double phase_scale, const void *grad_I, int n, int dtype,
-                          void *grad_phi_out, double *phi_dot_grad_out, void *hip_stream);
+                          double phase_scale, const void *grad_I, const void *field, int n,
+                          int dtype, void *grad_phi_out, double *phi_dot_grad_out,
+                          void *hip_stream);
 
 /*
  * fresnel_aperture -- the paper's own numerics for a bounded screen

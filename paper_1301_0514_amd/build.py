@@ -29,7 +29,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 PROGRAMS = ["ProgNoise", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgPropIntensity",
             "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX",
-            "ProgApertureX", "ProgAbs2"]
+            "ProgPropField", "ProgVjpYField", "ProgApertureX", "ProgAbs2"]
 # programs built for float only (their side transposes are complex64)
 PROGRAMS_F32 = ["ProgNoiseT", "ProgPhasePropT", "ProgPropIntensityT", "ProgRealFwdT", "ProgSmearMidT", "ProgInvReT"]
 

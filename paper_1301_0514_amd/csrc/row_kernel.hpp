@@ -798,6 +798,11 @@ using ProgVjpY = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_M
                         ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
 using ProgVjpX = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_GRAD_PHI, ROP_STORE_R,
                         ROP_DOT_R>;
+// the second propagation pass keeping the field A as the adjoint's
+// checkpoint beside |A|^2, and the adjoint's first pass starting from it
+using ProgPropField = OpList<ROP_LOAD_C, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C, ROP_ACC_ABS2U,
+                             ROP_STORE_ACC>;
+using ProgVjpYField = OpList<ROP_LOAD_C, ROP_MUL_RLOAD, ROP_FFT_FWD, ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;
 // aperture mode: windowed, chirped exp(i s phi) -> DFT along the row; then
 // DFT along the other axis and |.|^2
 using ProgApertureX = OpList<ROP_LOAD_PHASE, ROP_MUL_TAB, ROP_MUL_ROWTAB, ROP_FFT_FWD, ROP_STORE_C>;

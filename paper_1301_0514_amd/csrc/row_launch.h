@@ -18,6 +18,8 @@ struct ProgFwdReTag;
 struct ProgSmearMidTag;
 struct ProgInvReTag;
 struct ProgVjpYTag;
+struct ProgPropFieldTag;
+struct ProgVjpYFieldTag;
 struct ProgVjpXTag;
 struct ProgApertureXTag;
 struct ProgAbs2Tag;

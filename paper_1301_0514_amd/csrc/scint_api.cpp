@@ -410,6 +410,8 @@ SCINT_PROG_NAME(ProgFwdRe)
 SCINT_PROG_NAME(ProgSmearMid)
 SCINT_PROG_NAME(ProgInvRe)
 SCINT_PROG_NAME(ProgVjpY)
+SCINT_PROG_NAME(ProgPropField)
+SCINT_PROG_NAME(ProgVjpYField)
 SCINT_PROG_NAME(ProgVjpX)
 SCINT_PROG_NAME(ProgApertureX)
 SCINT_PROG_NAME(ProgAbs2)
@@ -773,6 +775,33 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
                      2 * (int)real_bytes(dtype), stream);
 }
 
+// Second propagation pass of nb screens (rows x of the transposed field W2:
+// DFT along y, chirp, inverse DFT, |.|^2 into Iacc, transposed layout).  With
+// F non-NULL the field A itself is kept there too, [b][x][y] complex, as the
+// adjoint's checkpoint.
+int prop_y_pass(int N, int dtype, int nb, const void *W2, const void *H, void *Iacc, void *F, hipStream_t stream) {
+    ProgBuilder d(N, (int64_t)nb * N);
+    if (F) {
+        d.op(ROP_LOAD_C, W2, nn(N), N)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H)
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, F, nn(N), N)
+            .op(ROP_ACC_ABS2U)
+            .op(ROP_STORE_ACC, Iacc, nn(N), N);
+        return run_row<ProgPropFieldTag>(dtype, N, d.p, d.n, stream);
+    }
+    d.op(ROP_LOOP)
+        .op(ROP_LOAD_C, W2, nn(N), N)
+        .op(ROP_FFT_FWD)
+        .op(ROP_MUL_TAB, H)
+        .op(ROP_FFT_INV)
+        .op(ROP_ACC_ABS2U)
+        .op(ROP_ENDLOOP)
+        .op(ROP_STORE_ACC, Iacc, nn(N), N);
+    return run_row<ProgPropIntensityTag>(dtype, N, d.p, d.n, stream);
+}
+
 // ------------------------------------------------------------ no-allocation path
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
@@ -976,17 +1005,21 @@ int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed, 
 }
 
 int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t seed, uint32_t first_realisation,
-                      int n_real, double lambda, double z, int dtype, void *phi_out, void *I_out, void *hip_stream) {
+                      int n_real, double lambda, double z, int dtype, void *phi_out, void *I_out, void *field_out,
+                      void *hip_stream) {
     g_last_error.clear();
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n_real)) return rc;
     if (!I_out) return fail(PS_E_NULL, "I_out is NULL");
-    if (int rc = check_aligned({I_out, phi_out})) return rc;
+    if (int rc = check_aligned({I_out, phi_out, field_out})) return rc;
     if (!finite_pos(delta) || !finite_pos(r_diff) || !finite_pos(lambda) || !finite_pos(z))
         return fail(PS_E_PARAM, "delta, r_diff, lambda and z must be finite and > 0");
     if (!(std::isfinite(beta) && beta > 2.0 && beta < 4.0)) return fail(PS_E_PARAM, "beta must lie in (2, 4)");
     const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n_real;
     if (phi_out && overlaps(phi_out, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "phi_out overlaps I_out");
+    if (field_out && (overlaps(field_out, 2 * rbytes, I_out, rbytes) ||
+                      (phi_out && overlaps(field_out, 2 * rbytes, phi_out, rbytes))))
+        return fail(PS_E_ALIAS, "field_out overlaps I_out or phi_out");
     if (delta >= r_diff / 2.0) g_last_warning = "pixel side >= R_diff/2: the phase variations are undersampled";
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
@@ -1021,16 +1054,8 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
             .op(ROP_STORE_C, W1, nn(N), N);
         if (int rc = run_row<ProgScreenPropTag>(dtype, N, b.p, b.n, stream)) return rc;
         if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
-        ProgBuilder d(N, (int64_t)nb * N);
-        d.op(ROP_LOOP)
-            .op(ROP_LOAD_C, W2, nn(N), N)
-            .op(ROP_FFT_FWD)
-            .op(ROP_MUL_TAB, H)
-            .op(ROP_FFT_INV)
-            .op(ROP_ACC_ABS2U)
-            .op(ROP_ENDLOOP)
-            .op(ROP_STORE_ACC, W1, nn(N), N);
-        if (int rc = run_row<ProgPropIntensityTag>(dtype, N, d.p, d.n, stream)) return rc;
+        char *F = field_out ? static_cast<char *>(field_out) + (size_t)b0 * cbytes : nullptr;
+        if (int rc = prop_y_pass(N, dtype, nb, W2, H, W1, F, stream)) return rc;
         char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
         if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
     }
@@ -1311,6 +1336,54 @@ int fresnel_propagate_noalloc(int N, double delta, double lambda, double z, cons
         .op(ROP_STORE_ACC, W1, nn(N), N);
     if (int rc = launch_row_plan0<ProgPropIntensityTag>(dtype, N, y.p, TW, stream)) return rc;
     HIP_TRY(launch_transpose(W1, I_out, N, n, (int)rb, stream));
+    return PS_OK;
+}
+
+int fresnel_propagate_field(int N, double delta, double lambda, double z, const void *phi, double phase_scale, int n,
+                            int dtype, void *I_out, void *field_out, void *hip_stream) {
+    g_last_error.clear();
+    g_last_warning.clear();
+    if (int rc = check_common(N, dtype, n)) return rc;
+    if (!phi || !I_out || !field_out) return fail(PS_E_NULL, "phi, I_out and field_out must be non-NULL");
+    if (int rc = check_aligned({phi, I_out, field_out})) return rc;
+    if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
+        return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
+    if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
+    const size_t rbytes = (size_t)nn(N) * real_bytes(dtype) * n;
+    if (overlaps(phi, rbytes, I_out, rbytes)) return fail(PS_E_ALIAS, "I_out overlaps phi");
+    if (overlaps(field_out, 2 * rbytes, phi, rbytes) || overlaps(field_out, 2 * rbytes, I_out, rbytes))
+        return fail(PS_E_ALIAS, "field_out overlaps phi or I_out");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const double rho = std::sqrt(lambda * z / (2.0 * kPiD)) / delta;
+    const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
+    const size_t tbytes = (size_t)N * 2 * real_bytes(dtype);
+    const int nb_max = (int)std::max<size_t>(1, workspace_budget() / (2 * cbytes));
+    for (int b0 = 0; b0 < n; b0 += nb_max) {
+        const int nb = std::min(nb_max, n - b0);
+        void *ws = nullptr;
+        if (int rc = get_workspace(stream, 2 * cbytes * nb + tbytes + 1024, &ws)) return rc;
+        Carver c;
+        char *base = static_cast<char *>(ws);
+        void *W1 = base + c.take(cbytes * nb);
+        void *W2 = base + c.take(cbytes * nb);
+        void *H = base + c.take(tbytes);
+        if (int rc = chirp_tables(H, N, {rho}, dtype, true, stream)) return rc;
+        const char *ph = static_cast<const char *>(phi) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        ProgBuilder a(N, (int64_t)nb * N);
+        a.op(ROP_LOOP)
+            .op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
+            .op(ROP_FFT_FWD)
+            .op(ROP_MUL_TAB, H)
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, W1, nn(N), N)
+            .op(ROP_ENDLOOP);
+        if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, a.n, stream)) return rc;
+        if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
+        char *F = static_cast<char *>(field_out) + (size_t)b0 * cbytes;
+        if (int rc = prop_y_pass(N, dtype, nb, W2, H, W1, F, stream)) return rc;
+        char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
+    }
     return PS_OK;
 }
 
@@ -1752,19 +1825,20 @@ int source_smear(int N, double delta, const void *I_in, const double *radii, int
 }
 
 int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const void *phi, double phase_scale,
-                          const void *grad_I, int n, int dtype, void *grad_phi_out, double *phi_dot_grad_out,
-                          void *hip_stream) {
+                          const void *grad_I, const void *field, int n, int dtype, void *grad_phi_out,
+                          double *phi_dot_grad_out, void *hip_stream) {
     g_last_error.clear();
     g_last_warning.clear();
     if (int rc = check_common(N, dtype, n)) return rc;
     if (!phi || !grad_I || !grad_phi_out) return fail(PS_E_NULL, "phi, grad_I and grad_phi_out must be non-NULL");
-    if (int rc = check_aligned({phi, grad_I, grad_phi_out})) return rc;
+    if (int rc = check_aligned({phi, grad_I, grad_phi_out, field})) return rc;
     if (!finite_pos(delta) || !finite_pos(lambda) || !finite_pos(z))
         return fail(PS_E_PARAM, "delta, lambda and z must be finite and > 0");
     if (!std::isfinite(phase_scale)) return fail(PS_E_PARAM, "phase_scale must be finite");
     const size_t rb1 = (size_t)nn(N) * real_bytes(dtype);
-    if (overlaps(grad_phi_out, rb1 * n, phi, rb1 * n) || overlaps(grad_phi_out, rb1 * n, grad_I, rb1 * n))
-        return fail(PS_E_ALIAS, "grad_phi_out overlaps phi or grad_I");
+    if (overlaps(grad_phi_out, rb1 * n, phi, rb1 * n) || overlaps(grad_phi_out, rb1 * n, grad_I, rb1 * n) ||
+        (field && overlaps(grad_phi_out, rb1 * n, field, 2 * rb1 * n)))
+        return fail(PS_E_ALIAS, "grad_phi_out overlaps phi, grad_I or field");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     if (phi_dot_grad_out)
         if (int rc = refuse_in_capture(stream, "returning phi_dot_grad_out to the host")) return rc;
@@ -1790,30 +1864,42 @@ int fresnel_propagate_vjp(int N, double delta, double lambda, double z, const vo
         if (int rc = chirp_tables(H, N, {rho}, dtype, true, stream)) return rc;
         const char *ph = static_cast<const char *>(phi) + (size_t)b0 * rb1;
         const char *gI = static_cast<const char *>(grad_I) + (size_t)b0 * rb1;
-        // forward x-propagation (recomputed; nothing is kept between calls)
-        ProgBuilder a(N, (int64_t)nb * N);
-        a.op(ROP_LOOP)
-            .op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
-            .op(ROP_FFT_FWD)
-            .op(ROP_MUL_TAB, H)
-            .op(ROP_FFT_INV)
-            .op(ROP_STORE_C, W1, nn(N), N)
-            .op(ROP_ENDLOOP);
-        if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, a.n, stream)) return rc;
-        if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
         if (int rc = transpose(gI, Gt, N, nb, (int)real_bytes(dtype), stream)) return rc;
-        // y-propagation to A (transposed), g_A = 2 grad_I A, adjoint y-propagation
-        ProgBuilder b(N, (int64_t)nb * N);
-        b.op(ROP_LOAD_C, W2, nn(N), N)
-            .op(ROP_FFT_FWD)
-            .op(ROP_MUL_TAB, H)
-            .op(ROP_FFT_INV)
-            .op(ROP_MUL_RLOAD, Gt, nn(N), N, 0, 0, 2.0)
-            .op(ROP_FFT_FWD)
-            .op(ROP_MUL_TAB, H, 0, 0, 0, RF_CONJ)
-            .op(ROP_FFT_INV)
-            .op(ROP_STORE_C, W1, nn(N), N);
-        if (int rc = run_row<ProgVjpYTag>(dtype, N, b.p, b.n, stream)) return rc;
+        if (field) {
+            // from the checkpoint: g_A = 2 grad_I A, adjoint y-propagation
+            ProgBuilder b(N, (int64_t)nb * N);
+            b.op(ROP_LOAD_C, static_cast<const char *>(field) + (size_t)b0 * cbytes, nn(N), N)
+                .op(ROP_MUL_RLOAD, Gt, nn(N), N, 0, 0, 2.0)
+                .op(ROP_FFT_FWD)
+                .op(ROP_MUL_TAB, H, 0, 0, 0, RF_CONJ)
+                .op(ROP_FFT_INV)
+                .op(ROP_STORE_C, W1, nn(N), N);
+            if (int rc = run_row<ProgVjpYFieldTag>(dtype, N, b.p, b.n, stream)) return rc;
+        } else {
+            // forward x-propagation (recomputed from phi)
+            ProgBuilder a(N, (int64_t)nb * N);
+            a.op(ROP_LOOP)
+                .op(ROP_LOAD_PHASE, ph, nn(N), N, 0, 0, phase_scale)
+                .op(ROP_FFT_FWD)
+                .op(ROP_MUL_TAB, H)
+                .op(ROP_FFT_INV)
+                .op(ROP_STORE_C, W1, nn(N), N)
+                .op(ROP_ENDLOOP);
+            if (int rc = run_row<ProgPhasePropTag>(dtype, N, a.p, a.n, stream)) return rc;
+            if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
+            // y-propagation to A (transposed), g_A = 2 grad_I A, adjoint y-propagation
+            ProgBuilder b(N, (int64_t)nb * N);
+            b.op(ROP_LOAD_C, W2, nn(N), N)
+                .op(ROP_FFT_FWD)
+                .op(ROP_MUL_TAB, H)
+                .op(ROP_FFT_INV)
+                .op(ROP_MUL_RLOAD, Gt, nn(N), N, 0, 0, 2.0)
+                .op(ROP_FFT_FWD)
+                .op(ROP_MUL_TAB, H, 0, 0, 0, RF_CONJ)
+                .op(ROP_FFT_INV)
+                .op(ROP_STORE_C, W1, nn(N), N);
+            if (int rc = run_row<ProgVjpYTag>(dtype, N, b.p, b.n, stream)) return rc;
+        }
         if (int rc = transpose(W1, W2, N, nb, (int)(cbytes / nn(N)), stream)) return rc;
         // adjoint x-propagation, dL/dphi = s Im(g_U conj U), and sum phi dL/dphi per row
         char *gphi = static_cast<char *>(grad_phi_out) + (size_t)b0 * rb1;

@@ -38,11 +38,13 @@ SIGNATURES = {
     "fresnel_propagate_noalloc": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_int, _c_int, _vp,
                                            _vp]),
     "ps_screen_fresnel": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _c_u64, _c_u32, _c_int, _c_dbl, _c_dbl,
-                                   _c_int, _vp, _vp, _vp]),
+                                   _c_int, _vp, _vp, _vp, _vp]),
+    "fresnel_propagate_field": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_int, _c_int, _vp, _vp,
+                                         _vp]),
     "illumination_polychromatic": (_c_int, [_c_int, _c_dbl, _c_dbl, _vp, _c_dbl, _dp, _dp, _c_int, _c_int,
                                             _c_int, _vp, _vp]),
     "source_smear": (_c_int, [_c_int, _c_dbl, _vp, _dp, _c_int, _c_int, _c_int, _vp, _vp]),
-    "fresnel_propagate_vjp": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _vp, _c_int, _c_int,
+    "fresnel_propagate_vjp": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _vp, _vp, _c_int, _c_int,
                                        _vp, _dp, _vp]),
     "ps_modulation_index": (_c_int, [_c_int, _vp, _c_int, _c_int, _dp, _dp, _vp]),
     "fresnel_aperture": (_c_int, [_c_int, _c_dbl, _c_dbl, _c_dbl, _vp, _c_dbl, _c_dbl, _c_int, _c_int, _vp, _vp]),
@@ -329,16 +331,33 @@ def aperture_geometry(N, delta, lam, z, r_diff, r_s=0.0):
 
 
 def ps_screen_fresnel(N, delta, r_diff, beta, seed, lam, z, first_realisation=0, n_real=1,
-                      dtype=torch.float32, want_phi=False, device=None):
-    """Screen generation and propagation fused; returns I (and phi if asked)."""
+                      dtype=torch.float32, want_phi=False, want_field=False, device=None):
+    """Screen generation and propagation fused; returns I, then phi and the
+    adjoint's field checkpoint [n_real, N, N, 2] ([b][x][y], re/im) if asked."""
     device = torch.device(device or "cuda")
     I = torch.empty((n_real, N, N), dtype=dtype, device=device)
     phi = torch.empty_like(I) if want_phi else None
+    field = torch.empty((n_real, N, N, 2), dtype=dtype, device=device) if want_field else None
     rc = load_library().ps_screen_fresnel(int(N), float(delta), float(r_diff), float(beta), int(seed),
                                           int(first_realisation), int(n_real), float(lam), float(z),
-                                          _dtype_code(dtype), _ptr(phi), _ptr(I), _stream(device))
+                                          _dtype_code(dtype), _ptr(phi), _ptr(I), _ptr(field), _stream(device))
     _check("ps_screen_fresnel", rc)
-    return (I, phi) if want_phi else I
+    out = (I,) + ((phi,) if want_phi else ()) + ((field,) if want_field else ())
+    return out if len(out) > 1 else I
+
+
+def fresnel_propagate_field(phi: torch.Tensor, delta, lam, z, phase_scale=1.0):
+    """(I, field): the pattern and the complex field A kept as the adjoint's
+    checkpoint, [..., N, N, 2] in the [b][x][y] layout; see scint.h."""
+    N = phi.shape[-1]
+    n = _batch_of(phi, N)
+    out = torch.empty_like(phi)
+    field = torch.empty(tuple(phi.shape) + (2,), dtype=phi.dtype, device=phi.device)
+    rc = load_library().fresnel_propagate_field(int(N), float(delta), float(lam), float(z), _ptr(phi),
+                                                float(phase_scale), n, _dtype_code(phi.dtype), _ptr(out), _ptr(field),
+                                                _stream(phi.device))
+    _check("fresnel_propagate_field", rc)
+    return out, field
 
 
 def illumination_polychromatic(phi_ref: torch.Tensor, delta, z, lam_ref, lambdas, weights=None,
@@ -376,19 +395,23 @@ def source_smear(I: torch.Tensor, delta, radii, out: torch.Tensor | None = None)
 
 
 def fresnel_propagate_vjp(phi: torch.Tensor, delta, lam, z, grad_I: torch.Tensor, phase_scale=1.0,
-                          out: torch.Tensor | None = None, want_dot=False):
-    """dL/dphi for dL/dI = grad_I; optionally also sum(phi * dL/dphi) per screen."""
+                          out: torch.Tensor | None = None, want_dot=False, field: torch.Tensor | None = None):
+    """dL/dphi for dL/dI = grad_I, from the forward's field checkpoint if
+    given (else the forward is recomputed); optionally also
+    sum(phi * dL/dphi) per screen."""
     N = phi.shape[-1]
     n = _batch_of(phi, N)
     _check_like("grad_I", grad_I, phi.shape, phi.dtype, phi.device)
+    if field is not None:
+        _check_like("field", field, tuple(phi.shape) + (2,), phi.dtype, phi.device)
     if out is None:
         out = torch.empty_like(phi)
     else:
         _check_like("out", out, phi.shape, phi.dtype, phi.device)
     dots = (ctypes.c_double * n)() if want_dot else None
     rc = load_library().fresnel_propagate_vjp(int(N), float(delta), float(lam), float(z), _ptr(phi),
-                                              float(phase_scale), _ptr(grad_I), n, _dtype_code(phi.dtype),
-                                              _ptr(out), dots, _stream(phi.device))
+                                              float(phase_scale), _ptr(grad_I), _ptr(field), n,
+                                              _dtype_code(phi.dtype), _ptr(out), dots, _stream(phi.device))
     _check("fresnel_propagate_vjp", rc)
     return (out, [dots[i] for i in range(n)]) if want_dot else out
 
@@ -503,19 +526,23 @@ def capture_graph(fn, warmup: int = 1, stream: torch.cuda.Stream | None = None):
 
 # ------------------------------------------------------------------ autograd
 class FresnelIntensity(torch.autograd.Function):
-    """I = fresnel_propagate(phi) with the hand-written adjoint as backward."""
+    """I = fresnel_propagate(phi) with the hand-written adjoint as backward;
+    the forward keeps the complex field as the adjoint's checkpoint, so the
+    backward runs the adjoint passes only."""
 
     @staticmethod
     def forward(ctx, phi, delta, lam, z, phase_scale):
-        ctx.save_for_backward(phi)
+        phi = phi.contiguous()
+        I, field = fresnel_propagate_field(phi, delta, lam, z, phase_scale)
+        ctx.save_for_backward(phi, field)
         ctx.args = (delta, lam, z, phase_scale)
-        return fresnel_propagate(phi.contiguous(), delta, lam, z, phase_scale)
+        return I
 
     @staticmethod
     def backward(ctx, grad_I):
-        (phi,) = ctx.saved_tensors
+        phi, field = ctx.saved_tensors
         delta, lam, z, s = ctx.args
-        g = fresnel_propagate_vjp(phi.contiguous(), delta, lam, z, grad_I.contiguous(), s)
+        g = fresnel_propagate_vjp(phi, delta, lam, z, grad_I.contiguous(), s, field=field)
         return g, None, None, None, None
 
 

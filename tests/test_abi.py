@@ -93,8 +93,14 @@ def test_validation_codes(lib):
     r1 = (ctypes.c_double * 2)(1.0, 2.0)
     assert s(256, 1.0, ok, r1, 2, 1, 0, ok, None) == -7  # in place needs n_r == 1
     v = lib.fresnel_propagate_vjp
-    assert v(256, 1.0, 1.0, 1.0, ok, 1.0, other, 1, 0, ok, None, None) == -7
-    assert v(256, 1.0, 1.0, 1.0, ok, 1.0, None, 1, 0, other, None, None) == -1
+    assert v(256, 1.0, 1.0, 1.0, ok, 1.0, other, None, 1, 0, ok, None, None) == -7
+    assert v(256, 1.0, 1.0, 1.0, ok, 1.0, None, None, 1, 0, other, None, None) == -1
+    # the field checkpoint must not overlap the gradient it feeds
+    third = _vp(1 << 34)
+    assert v(256, 1.0, 1.0, 1.0, ok, 1.0, other, third, 1, 0, _vp((1 << 34) + 1024), None, None) == -7
+    f = lib.fresnel_propagate_field
+    assert f(256, 1.0, 1.0, 1.0, ok, 1.0, 1, 0, other, None, None) == -1
+    assert f(256, 1.0, 1.0, 1.0, ok, 1.0, 1, 0, other, _vp((1 << 30) + 4096), None) == -7
     assert lib.ps_modulation_index(256, ok, 1, 0, None, None, None) == -1
     assert lib.ps_l2_loss(256, ok, other, 1, 0, ok, None, None) == -7
 

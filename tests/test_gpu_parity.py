@@ -234,14 +234,25 @@ def test_vjp(S, oracle, dtype, N, rho, s):
         gI = gI.astype(np.float32).astype(np.float64)
     lam = 5e-7
     z = 2 * np.pi * rho ** 2 / lam
-    g, dots = S.fresnel_propagate_vjp(dev(phi, dtype), 1.0, lam, z, dev(gI, dtype), s, want_dot=True)
-    g = host(g)
+    phi_d = dev(phi, dtype)
+    # recomputing the forward field, and from the forward's checkpoint
+    g, dots = S.fresnel_propagate_vjp(phi_d, 1.0, lam, z, dev(gI, dtype), s, want_dot=True)
+    I_f, field = S.fresnel_propagate_field(phi_d, 1.0, lam, z, s)
+    g_c, dots_c = S.fresnel_propagate_vjp(phi_d, 1.0, lam, z, dev(gI, dtype), s, want_dot=True, field=field)
+    g, g_c, I_f, field = host(g), host(g_c), host(I_f), host(field)
     for b in range(2):
         ref = oracle.propagate_vjp(phi[b], rho, s, gI[b])
-        check_field(g[b], ref, dtype, rms_tol=2e-5)
-        ref_dot = (phi[b] * ref).sum()
         tol = 1e-9 if dtype == torch.float64 else 1e-4
-        assert abs(dots[b] - ref_dot) <= tol * (np.abs(phi[b] * ref).sum())
+        ref_dot = (phi[b] * ref).sum()
+        for gg, dd in ((g[b], dots[b]), (g_c[b], dots_c[b])):
+            check_field(gg, ref, dtype, rms_tol=2e-5)
+            assert abs(dd - ref_dot) <= tol * (np.abs(phi[b] * ref).sum())
+        # the checkpoint is the field A, [x][y], with |A|^2 the pattern
+        I_ref, A_ref = oracle.propagate(phi[b], rho, s, return_field=True)
+        A = field[b, ..., 0] + 1j * field[b, ..., 1]
+        check_field(np.abs(A.T) ** 2, I_ref, dtype)
+        assert np.abs(A.T - A_ref).max() < (1e-10 if dtype == torch.float64 else 1e-5) * np.abs(A_ref).max()
+        check_field(I_f[b], I_ref, dtype)
 
 
 def test_autograd_matches_vjp(S, oracle):
