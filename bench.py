@@ -101,7 +101,7 @@ def stored_float(kernel: str, key: str, plan_variant: int | None = None):
 def cpu_baseline_configs(O, presets, log) -> list:
     """The FP64 oracle timed on the host's cores, per named configuration,
     all cores and one thread: the median of three runs where one run takes
-    under 10 s, one run otherwise; a single-thread run estimated above 40 s
+    under 10 s, one run otherwise; a single-thread run estimated above 60 s
     (all-core time x threads) is skipped and the estimate is reported."""
     import numpy as np
 
@@ -147,7 +147,7 @@ def cpu_baseline_configs(O, presets, log) -> list:
         t, k = med(fn, 10.0)
         row["all_cores"] = {"threads": all_cores, "runs": k, "median_s": t, "value": pts / t}
         est = t * all_cores
-        if est <= 40.0:
+        if est <= 60.0:
             O.set_num_threads(1)
             t1, k1 = med(fn, 10.0)
             row["single_thread"] = {"threads": 1, "runs": k1, "median_s": t1, "value": pts / t1}
