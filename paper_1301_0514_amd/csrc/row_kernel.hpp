@@ -126,6 +126,21 @@ template <typename Real, int L, int V = 0> struct RowCfg {
 #define SCINT_WAVES_PER_EU 2
 #endif
     static constexpr int WAVES_PER_EU = SCINT_WAVES_PER_EU;
+    // Rows of 16000 and 20000: each FFT stage (and each loop iteration) sees
+    // an opaque copy of the thread index, so that the per-element LDS
+    // addresses, which the padding makes nonlinear in the element index for
+    // mixed radices, are formed where they are used.  Otherwise the compiler
+    // shares them between the forward and inverse transforms and across the
+    // wavelength loop, and at these sizes (up to 128 VGPRs for the
+    // 1000-thread plans) keeps them in scratch: up to 668 bytes per thread,
+    // reloaded right before the LDS writes.  Elsewhere the addresses stay in
+    // registers (a few programs spill 12-72 bytes), and forming them per
+    // stage costs more: about 10 % more VALU instructions in the
+    // instruction-bound 8192 passes, 5 % more time at 10000.
+#ifndef SCINT_REMAT_MIN_L
+#define SCINT_REMAT_MIN_L 16000
+#endif
+    static constexpr bool REMAT_T = L >= SCINT_REMAT_MIN_L && (L & (L - 1)) != 0;
 };
 
 // ---------------------------------------------------------------- FFT
@@ -198,20 +213,23 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<R
     constexpr int Ns = stage_ns<L, V>(s);
     constexpr int mode = tw_mode<L, V>(s);
     constexpr bool last = (s == P::NS - 1);
+    // t as seen by this stage's butterflies (see RowCfg::REMAT_T)
+    int ts = t;
+    if constexpr (RowCfg<Real, L, V>::REMAT_T) asm volatile("" : "+v"(ts));
     TwGroup<Real, R> tg;
     if constexpr (mode != 0 && RowCfg<Real, L, V>::TWC_ON) {
         // the thread's base twiddles, once for all its butterflies of the stage
         cpx<Real> bv[tw_nbase<R>()];
-        const cpx<Real> *src = twc + tw_cache_offset<L, V>(s) + (mode == 1 ? t % Ns : t) * tw_nbase<R>();
+        const cpx<Real> *src = twc + tw_cache_offset<L, V>(s) + (mode == 1 ? ts % Ns : ts) * tw_nbase<R>();
 #pragma unroll
         for (int b = 0; b < tw_nbase<R>(); ++b) bv[b] = src[b];
         tg.build(bv);
     }
-    stage_butterflies<Real, L, V, s, 0>(v, lds, t, tw, twc, tg);
+    stage_butterflies<Real, L, V, s, 0>(v, lds, ts, tw, twc, tg);
     if constexpr (!last) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(t + m * T)];
+        for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(ts + m * T)];
         __syncthreads();
         fft_stage<Real, L, V, s + 1>(v, lds, t, tw, twc);
     }
@@ -639,7 +657,11 @@ __device__ __forceinline__ void run_ops(RowState<Real, L, V> &st) {
         if constexpr (c == ROP_LOOP) {
             constexpr int e = find_endloop<Ops>(I);
 #pragma clang loop unroll(disable)
-            for (st.it = st.it0; st.it < st.it1; ++st.it) run_ops<Real, L, V, Ops, I + 1, e>(st);
+            for (st.it = st.it0; st.it < st.it1; ++st.it) {
+                // (RowCfg::REMAT_T: addresses formed again per iteration)
+                if constexpr (RowCfg<Real, L, V>::REMAT_T) asm volatile("" : "+v"(st.t));
+                run_ops<Real, L, V, Ops, I + 1, e>(st);
+            }
             st.it = 0;
             run_ops<Real, L, V, Ops, e + 1, End>(st);
         } else {

@@ -161,3 +161,17 @@ def test_binding_rejects_mismatched_buffers():
     # on the host
     with pytest.raises(ValueError, match="GPU"):
         scint.fresnel_propagate(phi, 1.0, 5e-7, 1.0, out=torch.zeros_like(phi))
+
+
+def test_tune_plans_validates_before_the_device(lib):
+    assert lib.ps_tune_plans(257, 0) == -2
+    assert lib.ps_tune_plans(256, 5) == -4
+    assert lib.ps_tune_plans(16384, 1) == -2   # no FP64 plan at 16384
+    n = lib.fresnel_propagate_noalloc
+    ok, other = _vp(1 << 20), _vp(1 << 30)
+    assert n(256, 1.0, 1.0, 1.0, None, 1.0, 1, 0, ok, None) == -1
+    assert n(256, 1.0, 1.0, -1.0, ok, 1.0, 1, 0, other, None) == -3
+    assert n(256, 1.0, 1.0, 1.0, ok, 1.0, 1, 0, _vp((1 << 20) + 64), None) == -7
+    # a batch beyond the fixed scratch array is refused before any device call
+    assert n(2048, 1.0, 1.0, 1.0, ok, 1.0, 2, 0, other, None) == -2
+    assert b"scratch" in lib.ps_last_error()

@@ -72,3 +72,31 @@ def test_noalloc_rejects_batches_beyond_its_array(S):
     assert b"scratch" in lib.ps_last_error()
     torch.cuda.synchronize()
     assert bool((out == -1.0).all())
+
+
+def test_noalloc_captures_and_replays(S):
+    """Captured into a HIP graph (what the entry point is for), every replay,
+    with eager work and synchronisations between them, equals the eager call."""
+    N, n, rho = 512, 2, 16.0
+    lam = 5e-7
+    z = 2 * np.pi * rho ** 2 / lam
+    phi = torch.tensor(inputs.smooth_phase_field(N, seed=77, sigma=3.0, corr=3.0, n=n), dtype=torch.float32,
+                       device="cuda")
+    out = torch.empty_like(phi)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        S.fresnel_propagate_noalloc(phi, 1.0, lam, z, out=out)
+    stream.synchronize()
+    ref = out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        S.fresnel_propagate_noalloc(phi, 1.0, lam, z, out=out)
+    for rep in range(3):
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g.replay()
+        stream.synchronize()
+        assert torch.equal(out, ref), rep
+        S.fresnel_propagate(phi[:1], 1.0, lam, z)  # eager work between replays
+        torch.cuda.synchronize()
