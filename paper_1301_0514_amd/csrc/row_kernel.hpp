@@ -14,14 +14,17 @@ namespace scint {
 
 // LDS layout of a row: one padding slot every 32 elements breaks the
 // power-of-two strides of the Stockham writes across banks.  A row whose
-// padded length would not fit the 160 KB of LDS (20000 complex64) takes one
+// padded length would not fit the 160 KB of LDS (20000 complex64), or would
+// just miss the 80 KB that lets two workgroups share a CU (10000), takes one
 // slot every 64 elements.
 #ifndef SCINT_LDS_PAD_SHIFT
 #define SCINT_LDS_PAD_SHIFT 5
 #endif
 constexpr int kLdsPadShift = SCINT_LDS_PAD_SHIFT;
 template <int L> constexpr int lds_pad_shift() {
-    return (kLdsPadShift > 0 && (L + (L >> kLdsPadShift)) * 8 > 160 * 1024) ? 6 : kLdsPadShift;
+    if (kLdsPadShift <= 0 || kLdsPadShift >= 6) return kLdsPadShift;
+    const int b = (L + (L >> kLdsPadShift)) * 8, b6 = (L + (L >> 6)) * 8;
+    return (b > 160 * 1024 || (b > 80 * 1024 && b6 <= 80 * 1024)) ? 6 : kLdsPadShift;
 }
 template <int L> __device__ __forceinline__ int lds_index(int p) {
     constexpr int sh = lds_pad_shift<L>();
@@ -121,26 +124,35 @@ template <typename Real, int L, int V = 0> struct RowCfg {
     static constexpr int LDS_BYTES = USED_BYTES > RED_LDS_BYTES ? USED_BYTES : RED_LDS_BYTES;
     // lower bound on the occupancy the register allocator must keep: two
     // waves per SIMD (up to 256 VGPRs), which the heaviest programs need
-    // without spilling; lighter programs use fewer registers anyway
+    // without spilling; lighter programs use fewer registers anyway.  Rows of
+    // 10000 and more in 8-wave workgroups whose LDS lets two share a CU ask
+    // for four (up to 128 VGPRs), so that the registers let them too.
 #ifndef SCINT_WAVES_PER_EU
 #define SCINT_WAVES_PER_EU 2
 #endif
-    static constexpr int WAVES_PER_EU = SCINT_WAVES_PER_EU;
-    // Rows of 16000 and 20000: each FFT stage (and each loop iteration) sees
-    // an opaque copy of the thread index, so that the per-element LDS
-    // addresses, which the padding makes nonlinear in the element index for
-    // mixed radices, are formed where they are used.  Otherwise the compiler
+    static constexpr int WAVES_WG = (THREADS + 63) / 64;
+    static constexpr int WAVES_PER_EU =
+        (L >= 10000 && WAVES_WG == 8 && 2 * LDS_BYTES <= 160 * 1024 && SCINT_WAVES_PER_EU < 4) ? 4
+                                                                                                 : SCINT_WAVES_PER_EU;
+    // Mixed-radix rows of 10000 and more: each FFT stage (and each loop
+    // iteration) sees an opaque copy of the thread index, so that the
+    // per-element LDS addresses, which the padding makes nonlinear in the
+    // element index, are formed where they are used.  Otherwise the compiler
     // shares them between the forward and inverse transforms and across the
-    // wavelength loop, and at these sizes (up to 128 VGPRs for the
-    // 1000-thread plans) keeps them in scratch: up to 668 bytes per thread,
-    // reloaded right before the LDS writes.  Elsewhere the addresses stay in
-    // registers (a few programs spill 12-72 bytes), and forming them per
-    // stage costs more: about 10 % more VALU instructions in the
-    // instruction-bound 8192 passes, 5 % more time at 10000.
+    // wavelength loop, and under the 128 VGPRs of the 1000-thread plans (or
+    // of two 500-thread workgroups per CU at 10000) keeps them in scratch:
+    // up to 668 bytes per thread at 20000, reloaded right before the LDS
+    // writes.  The power-of-two rows keep them in registers (a few programs
+    // spill 12-72 bytes): forming them per stage there adds about 10 % to the
+    // VALU instructions of the instruction-bound 8192 passes, and made the
+    // 8192 smear 7 % slower.
 #ifndef SCINT_REMAT_MIN_L
-#define SCINT_REMAT_MIN_L 16000
+#define SCINT_REMAT_MIN_L 10000
 #endif
-    static constexpr bool REMAT_T = L >= SCINT_REMAT_MIN_L && (L & (L - 1)) != 0;
+#ifndef SCINT_REMAT_POW2
+#define SCINT_REMAT_POW2 0
+#endif
+    static constexpr bool REMAT_T = L >= SCINT_REMAT_MIN_L && (SCINT_REMAT_POW2 || (L & (L - 1)) != 0);
 };
 
 // ---------------------------------------------------------------- FFT
