@@ -404,8 +404,8 @@ int ps_tune_plans(int N, int dtype);
  * ps_set_workspace_budget -- upper bound, in bytes, on the workspace that
  * later calls on the current device plan for; whole-batch work is split into
  * chunks that fit it (the chunking can change FP32 rounding of sums over
- * wavelength chunks).  0 restores the default: half the free device memory
- * at the next call, at most 96 GiB.  Values below 64 MiB are rejected
+ * wavelength chunks).  0 restores the default: a quarter of the free device
+ * memory at the next call, at most 32 GiB.  Values below 64 MiB are rejected
  * (PS_E_PARAM).  A single grid that needs more than the budget still gets
  * the memory it needs.
  */

@@ -243,12 +243,15 @@ def test_fresnel_propagate_pipelined_equals_plain(S, monkeypatch, N, n):
 def test_pipelined_equals_plain_large_workgroups(S, monkeypatch, N):
     # row workgroups of 1000 (10000, ragged transpose units) and 512 threads
     # (16384): threads beyond 256 only take part in the side transposes'
-    # barriers.  Default budget: two pipelined jobs of one realisation against
-    # one plain job of both, the same sums
+    # barriers.  A 48 GiB budget: two pipelined jobs of one realisation and
+    # four wavelengths against one plain job of both, the same sums
     z, lam_ref, lams, w = geometry(N, 2, 4)
+    budget = 48 << 30
+    plan = S.plan_polychromatic(N, 2, 4, budget)
+    assert plan["pipelined"] and plan["n_jobs"] == 2 and plan["lambdas_per_job"] == 4
     phi = S.ps_generate(N, 1.0, N / 300.0, 11 / 3, 12, 0, 2)
-    a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, True)
-    b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, 0, False)
+    a = poly(S, monkeypatch, phi, z, lam_ref, lams, w, budget, True)
+    b = poly(S, monkeypatch, phi, z, lam_ref, lams, w, budget, False)
     assert torch.equal(a, b)
     assert float(a.mean()) == pytest.approx(1.0, abs=1e-5)
 
