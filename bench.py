@@ -10,6 +10,7 @@ phase ~ 1/lambda), co-added, and smeared by uniform stellar disks of radius
 Prints one JSON line on stdout; progress goes to stderr.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
+                  [--secondary NAME,...]
 """
 from __future__ import annotations
 
@@ -161,6 +162,11 @@ def cpu_baseline_configs(O, presets, log) -> list:
     return rows
 
 
+# the secondary configurations timed after the step, in order
+SECONDARY = ["batched_vs_plain", "single4096", "paper_scale", "aperture8192", "m_theory", "structure16000",
+             "ks20000", "grad2048"]
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,12 +174,20 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--secondary", default="all",
+                    help="comma-separated secondary configurations to run (default all): " + ",".join(SECONDARY))
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="time eager calls instead of replays of the captured step")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="first copy this many GB device-to-device with one plain copy kernel, as the "
                          "reference of known size for the FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args(argv)
+    if args.secondary != "all":
+        bad = [n for n in args.secondary.split(",") if n not in SECONDARY]
+        if bad:
+            print("unknown secondary configuration(s) %s; choose from %s" % (bad, ",".join(SECONDARY)),
+                  file=sys.stderr)
+            return 2
     if args.gpus != 1:
         print("bench.py measures the single-GPU path only (one MI355X); --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -407,6 +421,10 @@ def main(argv=None) -> int:
     # ---------------------------------------------------------------- secondary configurations
     if not args.no_secondary:
         sec = {}
+        chosen = SECONDARY if args.secondary == "all" else args.secondary.split(",")
+
+        def want(name):
+            return name in chosen
 
         def timed(fn, reps):
             fn()
@@ -420,161 +438,169 @@ def main(argv=None) -> int:
             torch.cuda.synchronize()
             return a.elapsed_time(b) / reps
 
-        # plain single-wavelength path, 32 calls, against the batched call (one screen)
-        one = phi[0:1]
-        acc_plain = torch.empty_like(one)
-        tmp = torch.empty_like(one)
+        if want("batched_vs_plain"):
+            # plain single-wavelength path, 32 calls, against the batched call (one screen)
+            one = phi[0:1]
+            acc_plain = torch.empty_like(one)
+            tmp = torch.empty_like(one)
 
-        def plain():
-            acc_plain.zero_()
-            for lam in lams:
-                scint.fresnel_propagate(one, 1.0, lam, cfg.z, cfg.lam_ref / lam, out=tmp)
-                acc_plain.add_(tmp, alpha=1.0 / n_lam)
+            def plain():
+                acc_plain.zero_()
+                for lam in lams:
+                    scint.fresnel_propagate(one, 1.0, lam, cfg.z, cfg.lam_ref / lam, out=tmp)
+                    acc_plain.add_(tmp, alpha=1.0 / n_lam)
 
-        batched_out = torch.empty_like(one)
+            batched_out = torch.empty_like(one)
 
-        def batched():
-            scint.illumination_polychromatic(one, 1.0, cfg.z, cfg.lam_ref, lams, out=batched_out)
+            def batched():
+                scint.illumination_polychromatic(one, 1.0, cfg.z, cfg.lam_ref, lams, out=batched_out)
 
-        t_plain = timed(plain, 2)
-        t_batched = timed(batched, 3)
-        diff = (acc_plain - batched_out).abs().max().item()
-        sec["batched_vs_plain_single_lambda"] = {"ms_plain_32_calls": t_plain, "ms_batched": t_batched,
-                                                  "speedup": t_plain / t_batched, "max_abs_diff": diff}
-        log("batched vs plain: %.2f ms vs %.2f ms (x%.2f)" % (t_batched, t_plain, t_plain / t_batched))
-        del acc_plain, tmp, batched_out
+            t_plain = timed(plain, 2)
+            t_batched = timed(batched, 3)
+            diff = (acc_plain - batched_out).abs().max().item()
+            sec["batched_vs_plain_single_lambda"] = {"ms_plain_32_calls": t_plain, "ms_batched": t_batched,
+                                                      "speedup": t_plain / t_batched, "max_abs_diff": diff}
+            log("batched vs plain: %.2f ms vs %.2f ms (x%.2f)" % (t_batched, t_plain, t_plain / t_batched))
+            del acc_plain, tmp, batched_out
 
-        # single wavelength 4096^2, one screen+propagation per call, 12 calls
-        p4 = presets.SINGLE_4096
-        Iout = torch.empty((1, 4096, 4096), dtype=torch.float32, device=dev)
+        if want("single4096"):
+            # single wavelength 4096^2, one screen+propagation per call, 12 calls
+            p4 = presets.SINGLE_4096
+            Iout = torch.empty((1, 4096, 4096), dtype=torch.float32, device=dev)
 
-        def single4096():
-            for c in p4:
-                for s in c.seeds:
-                    r = scint.load_library().ps_screen_fresnel(
-                        c.N, 1.0, c.R, c.beta, s, 0, 1, c.lam, c.z, 0, None,
-                        scint._ptr(Iout), None, scint._stream(dev))
+            def single4096():
+                for c in p4:
+                    for s in c.seeds:
+                        r = scint.load_library().ps_screen_fresnel(
+                            c.N, 1.0, c.R, c.beta, s, 0, 1, c.lam, c.z, 0, None,
+                            scint._ptr(Iout), None, scint._stream(dev))
+                        if r != 0:
+                            raise RuntimeError("ps_screen_fresnel failed %d" % r)
+
+            t4 = timed(single4096, 3)
+            sec["single_4096_screen_fresnel"] = {"ms_per_12_calls": t4, "pt_per_s": 12 * 4096.0 ** 2 / (t4 / 1e3)}
+            log("4096^2 single lambda: %.3f ms per call" % (t4 / 12))
+            del Iout
+
+        if want("paper_scale"):
+            for c in presets.PAPER_SCALE:
+                if abs(c.beta - 11 / 3) > 1e-9:
+                    continue
+                out_t = torch.empty((1, c.N, c.N), dtype=torch.float32, device=dev)
+
+                def paper():
+                    r = scint.load_library().ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, 0, 1, c.lam, c.z, 0, None,
+                                                                scint._ptr(out_t), None, scint._stream(dev))
                     if r != 0:
                         raise RuntimeError("ps_screen_fresnel failed %d" % r)
 
-        t4 = timed(single4096, 3)
-        sec["single_4096_screen_fresnel"] = {"ms_per_12_calls": t4, "pt_per_s": 12 * 4096.0 ** 2 / (t4 / 1e3)}
-        log("4096^2 single lambda: %.3f ms per call" % (t4 / 12))
-        del Iout
+                tp = timed(paper, 3)
+                sec["paper_%d_screen_fresnel" % c.N] = {"ms_per_call": tp, "pt_per_s": c.N ** 2 / (tp / 1e3)}
+                log("%d^2 single lambda: %.3f ms" % (c.N, tp))
+                del out_t
 
-        for c in presets.PAPER_SCALE:
-            if abs(c.beta - 11 / 3) > 1e-9:
-                continue
-            out_t = torch.empty((1, c.N, c.N), dtype=torch.float32, device=dev)
+        if want("aperture8192"):
+            # aperture mode (one-FFT numerics with the window), 8192^2 at the
+            # conjugate relation N delta^2 = lambda z, on the bench's first screen
+            Na = 8192
+            phia = phi[:1] if phi.shape[-1] == Na else torch.zeros((1, Na, Na), dtype=torch.float32, device=dev)
+            lam_a = 2.162e-6
+            Ia = torch.empty_like(phia)
 
-            def paper():
-                r = scint.load_library().ps_screen_fresnel(c.N, 1.0, c.R, c.beta, 1, 0, 1, c.lam, c.z, 0, None,
-                                                            scint._ptr(out_t), None, scint._stream(dev))
+            def aperture():
+                scint.fresnel_aperture(phia, 1.0, lam_a, Na / lam_a, margin_rf=10.0, out=Ia)
+
+            ta = timed(aperture, 3)
+            sec["aperture_8192_fresnel"] = {"ms_per_call": ta, "pt_per_s": Na ** 2 / (ta / 1e3)}
+            log("aperture mode 8192^2: %.3f ms" % ta)
+            del Ia
+
+        if want("m_theory"):
+            # m against Eq. xparam (Sect. 4.1, Fig. mx), periodic mode on the
+            # paper's geometry, 16 realisations per configuration
+            from statistics import mean as _mean
+            from paper_1301_0514_amd import sweep
+            t0 = time.perf_counter()
+            pts = sweep.m_versus_theory(8192, 25.0, 2.162e-6, 160 * sweep.PC, 1000 * sweep.PC, [200, 300, 400, 500],
+                                        [0.25, 0.5], n_real=16, mode="periodic")
+            t_sweep = time.perf_counter() - t0
+            rows = []
+            for rd in (200, 300, 400, 500):
+                for rs in (0.25, 0.5):
+                    g = [p for p in pts if p.r_diff_km == rd and p.r_s_rsun == rs]
+                    rows.append({"r_diff_km": rd, "r_s_rsun": rs, "m_theory": g[0].m_theory,
+                                 "m_mean": _mean(p.m for p in g), "ratio_mean": _mean(p.m / p.m_theory for p in g),
+                                 "n_ref": g[0].n_ref})
+            sec["m_versus_theory_8192"] = {"seconds": t_sweep, "patterns": len(pts), "rows": rows}
+            log("m sweep: %d patterns in %.2f s" % (len(pts), t_sweep))
+
+        if want("structure16000"):
+            # structure-function check of a 16000^2 screen (Sect. 3.1.1): the
+            # paper's 540-km configuration (28.85 km pixels, R_diff = 500 km)
+            Ns = 16000
+            phis = scint.ps_generate(Ns, 28.85, 500.0, 11 / 3, 1, 0, 1, torch.float32, device=dev)
+            t0 = time.perf_counter()
+            _, rrec = scint.structure_function(phis, 28.85)
+            t_sf = time.perf_counter() - t0
+            sec["structure_function_16000"] = {"seconds_incl_first_use": t_sf, "rdiff_rec_km": rrec[0],
+                                               "rdiff_input_km": 500.0}
+            t0 = time.perf_counter()
+            scint.structure_function(phis, 28.85)
+            sec["structure_function_16000"]["seconds"] = time.perf_counter() - t0
+            log("structure function 16000^2: R_diff^rec %.1f km (input 500 km), %.3f s" % (
+                rrec[0], sec["structure_function_16000"]["seconds"]))
+            del phis
+
+        if want("ks20000"):
+            # the paper's scale: one 20000^2 screen through the 21-wavelength K_s
+            # band (Sect. 3.2.4)
+            kc = presets.PAPER_KS_20000
+            phik = scint.ps_generate(kc.N, kc.delta, kc.r_diff, 11 / 3, kc.seed, 0, 1, torch.float32, device=dev)
+            Ik = torch.empty_like(phik)
+
+            def ks_band():
+                scint.illumination_polychromatic(phik, kc.delta, kc.z, kc.lam_ref, kc.lambdas(), out=Ik)
+
+            tk = timed(ks_band, 2)
+            sec["paper_ks_20000_21_lambda"] = {"ms_per_call": tk,
+                                               "pt_per_s": kc.N ** 2 * kc.n_lambda / (tk / 1e3),
+                                               "m": scint.ps_modulation_index(Ik)[0]}
+            log("K_s band 20000^2 x 21 lambda: %.1f ms, m = %.3f" % (tk, sec["paper_ks_20000_21_lambda"]["m"]))
+            del phik, Ik
+
+        if want("grad2048"):
+            # forward + adjoint, 16 x 2048^2: the forward keeps the field as the
+            # adjoint's checkpoint; the recomputing adjoint is timed beside it
+            g = presets.GRAD_2048
+            nr = presets.GRAD_N_REAL
+            It = torch.empty((nr, g.N, g.N), dtype=torch.float32, device=dev)
+            for i in range(nr):
+                It[i:i + 1] = scint.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, presets.GRAD_TARGET_SEED0 + i, g.lam, g.z)
+            gphi = torch.empty_like(It)
+            Igr = torch.empty_like(It)
+            phig = torch.empty_like(It)
+            fieldg = torch.empty((nr, g.N, g.N, 2), dtype=torch.float32, device=dev)
+
+            def fwd_adj(checkpoint):
+                lib = scint.load_library()
+                st = scint._stream(dev)
+                r = lib.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, 1, 0, nr, g.lam, g.z, 0, scint._ptr(phig),
+                                          scint._ptr(Igr), scint._ptr(fieldg) if checkpoint else None, st)
                 if r != 0:
                     raise RuntimeError("ps_screen_fresnel failed %d" % r)
+                _, gI = scint.ps_l2_loss(Igr, It)
+                scint.fresnel_propagate_vjp(phig, 1.0, g.lam, g.z, gI, 1.0, out=gphi,
+                                            field=fieldg if checkpoint else None)
 
-            tp = timed(paper, 3)
-            sec["paper_%d_screen_fresnel" % c.N] = {"ms_per_call": tp, "pt_per_s": c.N ** 2 / (tp / 1e3)}
-            log("%d^2 single lambda: %.3f ms" % (c.N, tp))
-            del out_t
-
-        # aperture mode (one-FFT numerics with the window), 8192^2 at the
-        # conjugate relation N delta^2 = lambda z, on the bench's first screen
-        Na = 8192
-        phia = phi[:1] if phi.shape[-1] == Na else torch.zeros((1, Na, Na), dtype=torch.float32, device=dev)
-        lam_a = 2.162e-6
-        Ia = torch.empty_like(phia)
-
-        def aperture():
-            scint.fresnel_aperture(phia, 1.0, lam_a, Na / lam_a, margin_rf=10.0, out=Ia)
-
-        ta = timed(aperture, 3)
-        sec["aperture_8192_fresnel"] = {"ms_per_call": ta, "pt_per_s": Na ** 2 / (ta / 1e3)}
-        log("aperture mode 8192^2: %.3f ms" % ta)
-        del Ia
-
-        # m against Eq. xparam (Sect. 4.1, Fig. mx), periodic mode on the
-        # paper's geometry, 16 realisations per configuration
-        from statistics import mean as _mean
-        from paper_1301_0514_amd import sweep
-        t0 = time.perf_counter()
-        pts = sweep.m_versus_theory(8192, 25.0, 2.162e-6, 160 * sweep.PC, 1000 * sweep.PC, [200, 300, 400, 500],
-                                    [0.25, 0.5], n_real=16, mode="periodic")
-        t_sweep = time.perf_counter() - t0
-        rows = []
-        for rd in (200, 300, 400, 500):
-            for rs in (0.25, 0.5):
-                g = [p for p in pts if p.r_diff_km == rd and p.r_s_rsun == rs]
-                rows.append({"r_diff_km": rd, "r_s_rsun": rs, "m_theory": g[0].m_theory,
-                             "m_mean": _mean(p.m for p in g), "ratio_mean": _mean(p.m / p.m_theory for p in g),
-                             "n_ref": g[0].n_ref})
-        sec["m_versus_theory_8192"] = {"seconds": t_sweep, "patterns": len(pts), "rows": rows}
-        log("m sweep: %d patterns in %.2f s" % (len(pts), t_sweep))
-
-        # structure-function check of a 16000^2 screen (Sect. 3.1.1): the
-        # paper's 540-km configuration (28.85 km pixels, R_diff = 500 km)
-        Ns = 16000
-        phis = scint.ps_generate(Ns, 28.85, 500.0, 11 / 3, 1, 0, 1, torch.float32, device=dev)
-        t0 = time.perf_counter()
-        _, rrec = scint.structure_function(phis, 28.85)
-        t_sf = time.perf_counter() - t0
-        sec["structure_function_16000"] = {"seconds_incl_first_use": t_sf, "rdiff_rec_km": rrec[0],
-                                           "rdiff_input_km": 500.0}
-        t0 = time.perf_counter()
-        scint.structure_function(phis, 28.85)
-        sec["structure_function_16000"]["seconds"] = time.perf_counter() - t0
-        log("structure function 16000^2: R_diff^rec %.1f km (input 500 km), %.3f s" % (
-            rrec[0], sec["structure_function_16000"]["seconds"]))
-        del phis
-
-        # the paper's scale: one 20000^2 screen through the 21-wavelength K_s
-        # band (Sect. 3.2.4)
-        kc = presets.PAPER_KS_20000
-        phik = scint.ps_generate(kc.N, kc.delta, kc.r_diff, 11 / 3, kc.seed, 0, 1, torch.float32, device=dev)
-        Ik = torch.empty_like(phik)
-
-        def ks_band():
-            scint.illumination_polychromatic(phik, kc.delta, kc.z, kc.lam_ref, kc.lambdas(), out=Ik)
-
-        tk = timed(ks_band, 2)
-        sec["paper_ks_20000_21_lambda"] = {"ms_per_call": tk,
-                                           "pt_per_s": kc.N ** 2 * kc.n_lambda / (tk / 1e3),
-                                           "m": scint.ps_modulation_index(Ik)[0]}
-        log("K_s band 20000^2 x 21 lambda: %.1f ms, m = %.3f" % (tk, sec["paper_ks_20000_21_lambda"]["m"]))
-        del phik, Ik
-
-        # forward + adjoint, 16 x 2048^2: the forward keeps the field as the
-        # adjoint's checkpoint; the recomputing adjoint is timed beside it
-        g = presets.GRAD_2048
-        nr = presets.GRAD_N_REAL
-        It = torch.empty((nr, g.N, g.N), dtype=torch.float32, device=dev)
-        for i in range(nr):
-            It[i:i + 1] = scint.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, presets.GRAD_TARGET_SEED0 + i, g.lam, g.z)
-        gphi = torch.empty_like(It)
-        Igr = torch.empty_like(It)
-        phig = torch.empty_like(It)
-        fieldg = torch.empty((nr, g.N, g.N, 2), dtype=torch.float32, device=dev)
-
-        def fwd_adj(checkpoint):
-            lib = scint.load_library()
-            st = scint._stream(dev)
-            r = lib.ps_screen_fresnel(g.N, 1.0, g.R, g.beta, 1, 0, nr, g.lam, g.z, 0, scint._ptr(phig),
-                                      scint._ptr(Igr), scint._ptr(fieldg) if checkpoint else None, st)
-            if r != 0:
-                raise RuntimeError("ps_screen_fresnel failed %d" % r)
-            _, gI = scint.ps_l2_loss(Igr, It)
-            scint.fresnel_propagate_vjp(phig, 1.0, g.lam, g.z, gI, 1.0, out=gphi,
-                                        field=fieldg if checkpoint else None)
-
-        tg = timed(lambda: fwd_adj(True), 3)
-        tr = timed(lambda: fwd_adj(False), 3)
-        # survey model: forward 44 B/pt (screen, field and pattern kept) +
-        # adjoint 36 B/pt
-        sec["grad_2048x16_forward_adjoint"] = {"ms_per_step": tg, "pt_per_s": nr * g.N ** 2 / (tg / 1e3),
-                                               "ms_per_step_recomputing_adjoint": tr,
-                                               "frac_of_hbm_roofline_80B_per_pt":
-                                                   80.0 * nr * g.N ** 2 / (tg / 1e3) / (HBM_PEAK_GBS * 1e9)}
-        log("16 x 2048^2 forward+adjoint: %.3f ms with the checkpoint, %.3f ms recomputing" % (tg, tr))
+            tg = timed(lambda: fwd_adj(True), 3)
+            tr = timed(lambda: fwd_adj(False), 3)
+            # survey model: forward 44 B/pt (screen, field and pattern kept) +
+            # adjoint 36 B/pt
+            sec["grad_2048x16_forward_adjoint"] = {"ms_per_step": tg, "pt_per_s": nr * g.N ** 2 / (tg / 1e3),
+                                                   "ms_per_step_recomputing_adjoint": tr,
+                                                   "frac_of_hbm_roofline_80B_per_pt":
+                                                       80.0 * nr * g.N ** 2 / (tg / 1e3) / (HBM_PEAK_GBS * 1e9)}
+            log("16 x 2048^2 forward+adjoint: %.3f ms with the checkpoint, %.3f ms recomputing" % (tg, tr))
         out["secondary"] = sec
 
     print(json.dumps(out), flush=True)

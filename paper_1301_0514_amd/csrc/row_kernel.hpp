@@ -5,6 +5,7 @@
 
 #include "device_common.hpp"
 #include "fft_plan.hpp"
+#include "lds_layout.hpp"
 #include "row_program.h"
 #include "transpose_tile.hpp"
 
@@ -12,20 +13,7 @@
 
 namespace scint {
 
-// LDS layout of a row: one padding slot every 32 elements breaks the
-// power-of-two strides of the Stockham writes across banks.  A row whose
-// padded length would not fit the 160 KB of LDS (20000 complex64), or would
-// just miss the 80 KB that lets two workgroups share a CU (10000), takes one
-// slot every 64 elements.
-#ifndef SCINT_LDS_PAD_SHIFT
-#define SCINT_LDS_PAD_SHIFT 5
-#endif
-constexpr int kLdsPadShift = SCINT_LDS_PAD_SHIFT;
-template <int L> constexpr int lds_pad_shift() {
-    if (kLdsPadShift <= 0 || kLdsPadShift >= 6) return kLdsPadShift;
-    const int b = (L + (L >> kLdsPadShift)) * 8, b6 = (L + (L >> 6)) * 8;
-    return (b > 160 * 1024 || (b > 80 * 1024 && b6 <= 80 * 1024)) ? 6 : kLdsPadShift;
-}
+// position of element p in an exchange of the fixed layout
 template <int L> __device__ __forceinline__ int lds_index(int p) {
     constexpr int sh = lds_pad_shift<L>();
     return sh > 0 ? p + (p >> sh) : p;
@@ -104,8 +92,9 @@ template <int R, long long C, long long M> struct TwConst {
 template <typename Real, int L, int V = 0> struct RowCfg {
     using P = Plan<L, V>;
     static constexpr int T = P::T;
-    static constexpr int LDS_STRIDE = lds_pad_shift<L>() > 0 ? L + (L >> lds_pad_shift<L>()) : L;
     static constexpr int ELEM = 2 * (int)sizeof(Real);
+    // elements of a row's exchange buffer (the largest exchange layout)
+    static constexpr int LDS_STRIDE = exch_buffer_length<L, V>(ELEM);
     static constexpr int B_THREADS = T >= 256 ? 1 : 256 / T;
     static constexpr int B_LDS = (P::NS > 1) ? ((65536 / (LDS_STRIDE * ELEM)) > 0 ? 65536 / (LDS_STRIDE * ELEM) : 1)
                                              : B_THREADS;
@@ -240,8 +229,17 @@ __device__ __forceinline__ void fft_stage(cpx<Real> (&v)[(Plan<L, V>::E)], cpx<R
     stage_butterflies<Real, L, V, s, 0>(v, lds, ts, tw, twc, tg);
     if constexpr (!last) {
         __syncthreads();
+        constexpr ExchLayout lay = exch_layout<L, V>(s, 2 * (int)sizeof(Real));
+        if constexpr (lay.linear) {
+            // f(t + m T) = f(t) + m (T + T / P): one address, then offsets
+            constexpr int step = T + (lay.P > 0 ? T / lay.P : 0);
+            const int q = lay.P > 0 ? ts + (int)((unsigned)ts / (unsigned)lay.P) : ts;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(ts + m * T)];
+            for (int m = 0; m < E; ++m) v[m] = lds[q + m * step];
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) v[m] = lds[lds_index<L>(ts + m * T)];
+        }
         __syncthreads();
         fft_stage<Real, L, V, s + 1>(v, lds, t, tw, twc);
     }
@@ -282,8 +280,18 @@ __device__ __forceinline__ void stage_butterflies(cpx<Real> (&v)[(Plan<L, V>::E)
             for (int r = 0; r < R; ++r) v[i + r * Q] = a[r];
         } else {
             const int base = (j - k) * R + k;
+            constexpr ExchLayout lay = exch_layout<L, V>(s, 2 * (int)sizeof(Real));
+            if constexpr (lay.linear) {
+                // f(base + r Ns) = f(base) + r (Ns + Ns / P) if P divides Ns,
+                // f(base) + r Ns if the butterfly's outputs share one period
+                constexpr int step = Ns + ((lay.P > 0 && Ns % lay.P == 0) ? Ns / lay.P : 0);
+                const int q = lay.P > 0 ? base + (int)((unsigned)base / (unsigned)lay.P) : base;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_index<L>(base + r * Ns)] = a[r];
+                for (int r = 0; r < R; ++r) lds[q + r * step] = a[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[lds_index<L>(base + r * Ns)] = a[r];
+            }
         }
         stage_butterflies<Real, L, V, s, i + 1>(v, lds, t, tw, twc, tg);
     }
