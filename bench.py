@@ -40,8 +40,8 @@ def log(*a):
 
 # device sources of the row-pass kernels (the FFT passes) and of the
 # transposes, the two kernel families that dominate the step
-ROW_KERNEL_SOURCES = ("device_common.hpp", "fft_plan.hpp", "row_program.h", "row_kernel.hpp", "row_launch.h",
-                      "transpose_tile.hpp",
+ROW_KERNEL_SOURCES = ("device_common.hpp", "fft_plan.hpp", "lds_layout.hpp", "row_program.h", "row_kernel.hpp",
+                      "row_launch.h", "transpose_tile.hpp",
                       "row_inst.hip", "twiddles.cpp")
 AUX_KERNEL_SOURCES = ("device_common.hpp", "aux_kernels.h", "aux_kernels.hip", "transpose_tile.hpp")
 
