@@ -27,11 +27,11 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libscint.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-PROGRAMS = ["ProgNoise", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgPropIntensity",
+PROGRAMS = ["ProgNoise", "ProgNoiseSwap", "ProgScreen", "ProgScreenProp", "ProgPhaseProp", "ProgPropIntensity",
             "ProgRealFwd", "ProgFwdRe", "ProgSmearMid", "ProgInvRe", "ProgVjpY", "ProgVjpX",
             "ProgPropField", "ProgVjpYField", "ProgApertureX", "ProgAbs2"]
 # programs built for float only (their side transposes are complex64)
-PROGRAMS_F32 = ["ProgNoiseT", "ProgPhasePropT", "ProgPropIntensityT", "ProgRealFwdT", "ProgSmearMidT", "ProgInvReT"]
+PROGRAMS_F32 = ["ProgNoiseT", "ProgNoiseSwapT", "ProgPhasePropT", "ProgPropIntensityT", "ProgRealFwdT", "ProgSmearMidT", "ProgInvReT"]
 
 # gfx950 only; packed FP32 instructions are disabled (the compiler would
 # otherwise form them from float code).

@@ -80,10 +80,12 @@ hipError_t launch_hankel(const double *S, int N, int nbatch, const double *radii
 //   G[b][y][k] = sqrt(2) (B(k) + conj(B(-k))) for 1 <= k <= K, sqrt(2) B(0)
 //                for k = 0, B(kx') = sum_{|ky'| <= K} c(kx', ky') exp(2 pi i ky' y / N),
 // so that sqrt(2) Re of their part of the inverse DFT is
-// Re sum_k G[b][y][k] exp(2 pi i k x / N).  C is scratch (nbatch W^2
-// complex doubles); G is [nbatch][N][K + 1] complex doubles.  K < N/2.
+// Re sum_k G[b][y][k] exp(2 pi i k x / N).  With swap the roles of x and y
+// (kx' and ky') are exchanged: G[b][x][k] for screens kept transposed,
+// [b][x][y].  C is scratch (nbatch W^2 complex doubles); G is
+// [nbatch][N][K + 1] complex doubles.  K < N/2.
 hipError_t launch_low_modes(void *C, void *G, int N, int K, int nbatch, uint32_t r0, uint32_t seed_lo,
-                            uint32_t seed_hi, double amp0, double neg_beta_4, hipStream_t stream);
+                            uint32_t seed_hi, double amp0, double neg_beta_4, hipStream_t stream, bool swap = false);
 
 // out[b] = scale * sum_blk partials[b * nblk + blk], fixed-order tree.
 hipError_t launch_finalize_sums(const double *partials, int nblk, int nbatch, double scale, double *out,

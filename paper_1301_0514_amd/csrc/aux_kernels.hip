@@ -84,6 +84,7 @@ struct LowModeArgs {
     int N, K;
     uint32_t r0, seed_lo, seed_hi;
     double amp0, neg_beta_4;
+    int swap;  // C[b][i][j] = c(kx' = j - K, ky' = i - K) instead
 };
 
 // C[b][i][j]: one workgroup per (i, b), thread j
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(64) void low_mode_coeff_kernel(double2 *C, LowModeA
     const int W = 2 * a.K + 1;
     const int i = blockIdx.x, b = blockIdx.y, j = threadIdx.x;
     if (j >= W) return;
-    const int fx = i - a.K, fy = j - a.K;
+    const int fx = (a.swap ? j : i) - a.K, fy = (a.swap ? i : j) - a.K;
     const int kx = fx < 0 ? fx + a.N : fx, ky = fy < 0 ? fy + a.N : fy;
     C[((int64_t)b * W + i) * W + j] =
         spectrum_coeff_f64(kx, ky, a.N, a.r0 + (uint32_t)b, a.seed_lo, a.seed_hi, a.amp0, a.neg_beta_4);
@@ -136,12 +137,12 @@ __global__ __launch_bounds__(64) void low_mode_rows_kernel(const double2 *__rest
 }
 
 hipError_t launch_low_modes(void *C, void *G, int N, int K, int nbatch, uint32_t r0, uint32_t seed_lo,
-                            uint32_t seed_hi, double amp0, double neg_beta_4, hipStream_t stream) {
+                            uint32_t seed_hi, double amp0, double neg_beta_4, hipStream_t stream, bool swap) {
     if (K < 0 || 2 * K + 1 > 64 || K >= N / 2 || nbatch < 1) return hipErrorInvalidValue;
     const int W = 2 * K + 1;
     for (int b0 = 0; b0 < nbatch; b0 += 65535) {
         const int nb = nbatch - b0 < 65535 ? nbatch - b0 : 65535;
-        LowModeArgs a{N, K, r0 + (uint32_t)b0, seed_lo, seed_hi, amp0, neg_beta_4};
+        LowModeArgs a{N, K, r0 + (uint32_t)b0, seed_lo, seed_hi, amp0, neg_beta_4, swap ? 1 : 0};
         double2 *Cb = static_cast<double2 *>(C) + (int64_t)b0 * W * W;
         double2 *Gb = static_cast<double2 *>(G) + (int64_t)b0 * N * (K + 1);
         hipLaunchKernelGGL(low_mode_coeff_kernel, dim3(W, nb), dim3(64), 0, stream, Cb, a);

@@ -531,6 +531,10 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
         const uint32_t r = (uint32_t)st.prog->r0 + (uint32_t)st.batch;
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = spectrum_coeff<Real>(st.row, st.t + m * T, L, r, *st.prog);
+    } else if constexpr (CODE == ROP_NOISE_SWAP) {
+        const uint32_t r = (uint32_t)st.prog->r0 + (uint32_t)st.batch;
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = spectrum_coeff<Real>(st.t + m * T, st.row, L, r, *st.prog);
     } else if constexpr (CODE == ROP_KEEP_R) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
 #pragma unroll
@@ -810,6 +814,9 @@ __attribute__((amdgpu_waves_per_eu(RowCfg<Real, L, V>::WAVES_PER_EU))) void row_
 using ProgNoise = OpList<ROP_NOISE, ROP_FFT_INV, ROP_STORE_C>;
 // the noise pass carrying the transpose of an earlier batch's output (RowSide)
 using ProgNoiseT = OpList<ROP_SIDE_T, ROP_NOISE, ROP_FFT_INV, ROP_STORE_C>;
+// the same along kx (rows ky), for screens made transposed
+using ProgNoiseSwap = OpList<ROP_NOISE_SWAP, ROP_FFT_INV, ROP_STORE_C>;
+using ProgNoiseSwapT = OpList<ROP_SIDE_T, ROP_NOISE_SWAP, ROP_FFT_INV, ROP_STORE_C>;
 using ProgScreen = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R>;
 using ProgScreenProp = OpList<ROP_LOAD_C, ROP_FFT_INV, ROP_SQRT2RE, ROP_STORE_R, ROP_EXP_RE, ROP_FFT_FWD,
                               ROP_MUL_TAB, ROP_FFT_INV, ROP_STORE_C>;

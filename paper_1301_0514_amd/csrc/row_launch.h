@@ -9,6 +9,7 @@
 namespace scint {
 
 struct ProgNoiseTag;
+struct ProgNoiseSwapTag;
 struct ProgScreenTag;
 struct ProgScreenPropTag;
 struct ProgPhasePropTag;
@@ -24,6 +25,7 @@ struct ProgVjpXTag;
 struct ProgApertureXTag;
 struct ProgAbs2Tag;
 struct ProgNoiseTTag;          // complex64 only
+struct ProgNoiseSwapTTag;      // complex64 only
 struct ProgPhasePropTTag;     // complex64 only
 struct ProgPropIntensityTTag;  // complex64 only
 struct ProgRealFwdTTag;        // complex64 only

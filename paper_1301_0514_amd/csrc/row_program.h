@@ -44,6 +44,7 @@ enum RowOpCode : int32_t {
     ROP_MUL_ROWTAB,  // v *= tab[row]  (complex, one factor per row)
     ROP_SIDE_T,      // first op only: the launch also runs the transposes of RowProgram::side
     ROP_ACC_ABS2U,   // acc[e] += |v|^2, no weight (two fused multiply-adds per element)
+    ROP_NOISE_SWAP,  // ROP_NOISE with row = ky, element = kx (screens made transposed)
 };
 
 // Flag bits

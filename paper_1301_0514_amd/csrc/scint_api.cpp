@@ -401,6 +401,7 @@ template <class Tag> const char *prog_name();
 #define SCINT_PROG_NAME(P) \
     template <> const char *prog_name<P##Tag>() { return #P; }
 SCINT_PROG_NAME(ProgNoise)
+SCINT_PROG_NAME(ProgNoiseSwap)
 SCINT_PROG_NAME(ProgScreen)
 SCINT_PROG_NAME(ProgScreenProp)
 SCINT_PROG_NAME(ProgPhaseProp)
@@ -416,6 +417,7 @@ SCINT_PROG_NAME(ProgVjpX)
 SCINT_PROG_NAME(ProgApertureX)
 SCINT_PROG_NAME(ProgAbs2)
 SCINT_PROG_NAME(ProgNoiseT)
+SCINT_PROG_NAME(ProgNoiseSwapT)
 SCINT_PROG_NAME(ProgPhasePropT)
 SCINT_PROG_NAME(ProgPropIntensityT)
 SCINT_PROG_NAME(ProgRealFwdT)
@@ -647,9 +649,11 @@ size_t low_mode_bytes(int N, int nb, int dtype) {
 // transforms carry the Fourier modes outside the square |kx'|, |ky'| <= K,
 // and the second screen pass adds the square's part, summed in FP64 from the
 // row table built here at `tab` (low_mode_bytes of workspace), to the
-// screen.  Sets p.low_k and p.low_tab of that pass (nothing for FP64).
+// screen.  Sets p.low_k and p.low_tab of that pass (nothing for FP64).  With
+// swap the table serves screens made transposed ([b][x][y]; screen_passes
+// with swap).
 int low_mode_pass(RowProgram &p, int N, double R, double beta, uint64_t seed, uint32_t r0, int nb, int dtype,
-                  void *tab, hipStream_t stream) {
+                  void *tab, hipStream_t stream, bool swap) {
     if (dtype != PS_F32) return PS_OK;
     RowProgram q;
     std::memset(&q, 0, sizeof(q));
@@ -657,7 +661,7 @@ int low_mode_pass(RowProgram &p, int N, double R, double beta, uint64_t seed, ui
     const int K = q.low_k;
     char *G = static_cast<char *>(tab);
     char *C = G + (size_t)nb * N * (K + 1) * 16;
-    HIP_TRY(launch_low_modes(C, G, N, K, nb, r0, q.seed_lo, q.seed_hi, q.amp0, q.neg_beta_4, stream));
+    HIP_TRY(launch_low_modes(C, G, N, K, nb, r0, q.seed_lo, q.seed_hi, q.amp0, q.neg_beta_4, stream, swap));
     p.low_k = K;
     p.low_tab = G;
     return PS_OK;
@@ -745,9 +749,11 @@ static SideCfg side_cfg() {
 // carries the transpose of job k-1 as extra workgroups (its arithmetic-bound
 // FFTs leave memory bandwidth free), and only the last job's transpose runs
 // on its own.  Each element is computed by the same kernel code either way,
-// so the results do not depend on the split.
+// so the results do not depend on the split.  With swap the first pass runs
+// along kx instead (rows ky), so that the second pass makes the screens
+// transposed, [b][x][y].
 int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int nb, int dtype, void *W1, void *W2,
-                  hipStream_t stream) {
+                  hipStream_t stream, bool swap) {
     const SideCfg sc = side_cfg();
     const int J = (dtype == PS_F32 && N >= 2048 && sc.on) ? std::min(nb, sc.screen_jobs) : 1;
     const size_t cbytes = (size_t)nn(N) * 2 * real_bytes(dtype);
@@ -758,9 +764,13 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
         ProgBuilder a(N, (int64_t)jn * N);
         set_noise(a.p, N, R, beta, seed, r0 + (uint32_t)j0, dtype);
         if (k > 0) a.op(ROP_SIDE_T);
-        a.op(ROP_NOISE).op(ROP_FFT_INV).op(ROP_STORE_C, static_cast<char *>(W1) + j0 * cbytes, nn(N), N);
+        a.op(swap ? ROP_NOISE_SWAP : ROP_NOISE)
+            .op(ROP_FFT_INV)
+            .op(ROP_STORE_C, static_cast<char *>(W1) + j0 * cbytes, nn(N), N);
         if (k == 0) {
-            if (int rc = run_row<ProgNoiseTag>(dtype, N, a.p, a.n, stream)) return rc;
+            const int rc = swap ? run_row<ProgNoiseSwapTag>(dtype, N, a.p, a.n, stream)
+                                : run_row<ProgNoiseTag>(dtype, N, a.p, a.n, stream);
+            if (rc) return rc;
         } else {
             RowSide &sd = a.p.side;
             sd.in = static_cast<char *>(W1) + prev0 * cbytes;
@@ -769,7 +779,9 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
             sd.u1 = upm * prev_n;
             sd.fft_blocks = sc.fft_x;
             sd.side_blocks = sc.side_x;
-            if (int rc = run_row_side<ProgNoiseTTag>(N, a.p, a.n, stream)) return rc;
+            const int rc = swap ? run_row_side<ProgNoiseSwapTTag>(N, a.p, a.n, stream)
+                                : run_row_side<ProgNoiseTTag>(N, a.p, a.n, stream);
+            if (rc) return rc;
         }
         prev0 = j0;
         prev_n = jn;
@@ -779,7 +791,8 @@ int screen_passes(int N, double R, double beta, uint64_t seed, uint32_t r0, int 
 }
 
 // Second propagation pass of nb screens (rows x of the transposed field W2:
-// DFT along y, chirp, inverse DFT, |.|^2 into Iacc, transposed layout).  With
+// DFT along y, chirp, inverse DFT, |.|^2 into Iacc, transposed layout; for
+// screens made transposed, the same along x on rows y, natural layout).  With
 // F non-NULL the field A itself is kept there too, [b][x][y] complex, as the
 // adjoint's checkpoint.
 int prop_y_pass(int N, int dtype, int nb, const void *W2, const void *H, void *Iacc, void *F, hipStream_t stream) {
@@ -997,9 +1010,9 @@ int ps_generate(int N, double delta, double r_diff, double beta, uint64_t seed, 
         void *W1 = base + c.take(cbytes * nb);
         void *W2 = base + c.take(cbytes * nb);
         void *LT = base + c.take(low_mode_bytes(N, nb, dtype));
-        if (int rc = screen_passes(N, r_diff / delta, beta, seed, r0, nb, dtype, W1, W2, stream)) return rc;
+        if (int rc = screen_passes(N, r_diff / delta, beta, seed, r0, nb, dtype, W1, W2, stream, false)) return rc;
         ProgBuilder b(N, (int64_t)nb * N);
-        if (int rc = low_mode_pass(b.p, N, r_diff / delta, beta, seed, r0, nb, dtype, LT, stream)) return rc;
+        if (int rc = low_mode_pass(b.p, N, r_diff / delta, beta, seed, r0, nb, dtype, LT, stream, false)) return rc;
         char *phi = static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
         b.op(ROP_LOAD_C, W2, nn(N), N).op(ROP_FFT_INV).op(ROP_SQRT2RE).op(ROP_STORE_R, phi, nn(N), N, 0, 0, 1.0);
         if (int rc = run_row<ProgScreenTag>(dtype, N, b.p, b.n, stream)) return rc;
@@ -1042,10 +1055,17 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
         void *H = base + c.take(tbytes);
         void *LT = base + c.take(low_mode_bytes(N, nb, dtype));
         if (int rc = chirp_tables(H, N, {rho}, dtype, true, stream)) return rc;
-        if (int rc = screen_passes(N, r_diff / delta, beta, seed, r0, nb, dtype, W1, W2, stream)) return rc;
+        // Without the screen and the field to return, the screens are made
+        // transposed ([b][x][y]: the first pass along kx), the first
+        // propagation pass runs along y and the second along x, so that the
+        // pattern comes out of it in the natural layout and needs no final
+        // transpose.  With either returned, the natural order (screen rows y,
+        // the field's checkpoint layout [b][x][y]).
+        const bool swap = !phi_out && !field_out;
+        if (int rc = screen_passes(N, r_diff / delta, beta, seed, r0, nb, dtype, W1, W2, stream, swap)) return rc;
         char *phi = phi_out ? static_cast<char *>(phi_out) + (size_t)b0 * nn(N) * real_bytes(dtype) : nullptr;
         ProgBuilder b(N, (int64_t)nb * N);
-        if (int rc = low_mode_pass(b.p, N, r_diff / delta, beta, seed, r0, nb, dtype, LT, stream)) return rc;
+        if (int rc = low_mode_pass(b.p, N, r_diff / delta, beta, seed, r0, nb, dtype, LT, stream, swap)) return rc;
         b.op(ROP_LOAD_C, W2, nn(N), N)
             .op(ROP_FFT_INV)
             .op(ROP_SQRT2RE)
@@ -1058,8 +1078,12 @@ int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t 
         if (int rc = run_row<ProgScreenPropTag>(dtype, N, b.p, b.n, stream)) return rc;
         if (int rc = transpose(W1, W2, N, nb, 2 * (int)real_bytes(dtype), stream)) return rc;
         char *F = field_out ? static_cast<char *>(field_out) + (size_t)b0 * cbytes : nullptr;
-        if (int rc = prop_y_pass(N, dtype, nb, W2, H, W1, F, stream)) return rc;
         char *I = static_cast<char *>(I_out) + (size_t)b0 * nn(N) * real_bytes(dtype);
+        if (swap) {
+            if (int rc = prop_y_pass(N, dtype, nb, W2, H, I, nullptr, stream)) return rc;
+            continue;
+        }
+        if (int rc = prop_y_pass(N, dtype, nb, W2, H, W1, F, stream)) return rc;
         if (int rc = transpose(W1, I, N, nb, (int)real_bytes(dtype), stream)) return rc;
     }
     return PS_OK;

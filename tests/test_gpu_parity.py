@@ -149,6 +149,12 @@ def test_screen_fresnel(S, oracle, dtype, N, R, rho):
     phi2 = host(S.ps_generate(N, 1.0, R, 11 / 3, 1, 0, 2, dtype))
     ulp = np.finfo(np.float64 if dtype == torch.float64 else np.float32).eps
     assert np.abs(phi - phi2).max() <= 8 * ulp * np.abs(phi).max()
+    # without the screen returned the screens are made transposed and the
+    # two propagation passes run in the other order (no final transpose):
+    # the same pattern against the oracle
+    I3 = host(S.ps_screen_fresnel(N, 1.0, R, 11 / 3, 1, lam, z, first_realisation=0, n_real=2, dtype=dtype))
+    for b in range(2):
+        check_intensity(I3[b], oracle.propagate(oracle.screen(N, R, 11 / 3, 1, b), rho), dtype)
 
 
 # ------------------------------------------------------------------ polychromatic

@@ -306,6 +306,21 @@ def test_screen_pipelined_equals_plain(S, monkeypatch, N, n_real, jobs):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("N,n_real,jobs", [(2048, 8, "4"), (4000, 5, "4")])
+def test_transposed_screens_pipelined_equals_plain(S, monkeypatch, N, n_real, jobs):
+    # ps_screen_fresnel without the screen returned makes its screens
+    # transposed (noise along kx): the job split leaves every element's
+    # arithmetic alike there too
+    lam = 5e-7
+    z = 2 * np.pi * (N / 20.0) ** 2 / lam
+    monkeypatch.setenv("SCINT_SCREEN_JOBS", jobs)
+    a = S.ps_screen_fresnel(N, 1.0, N / 100.0, 11 / 3, 5, lam, z, first_realisation=7, n_real=n_real)
+    monkeypatch.setenv("SCINT_SCREEN_JOBS", "1")
+    b = S.ps_screen_fresnel(N, 1.0, N / 100.0, 11 / 3, 5, lam, z, first_realisation=7, n_real=n_real)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_screen_pipelined_vs_oracle(S, oracle, monkeypatch):
     # eight realisations in four jobs: realisation 1 is transposed on the
     # second job's noise pass, realisation 7 by the last, standalone transpose
