@@ -363,9 +363,12 @@ __device__ __forceinline__ cpx<float> spectrum_coeff<float>(int kx, int ky, int 
     const uint64_t b = ((uint64_t)w.x2 << 32) | w.x3;
     const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
     const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
-    const float rad = sqrtf(-2.0f * logf((float)u1));
-    float sn, cs;
-    sincospif((float)(2.0 * (u2 - rint(u2))), &sn, &cs);
+    // hardware transcendentals, their arguments in range by construction:
+    // -2 ln u1 = -2 ln 2 log2 u1 (u1 >= 2^-54, a normal float); the angle
+    // 2 pi (u2 - rint(u2)) as the turns the hardware sine and cosine take
+    const float rad = sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf((float)u1));
+    const float turn = (float)(u2 - rint(u2));
+    const float sn = __builtin_amdgcn_sinf(turn), cs = __builtin_amdgcn_cosf(turn);
     const int fx = kx < N / 2 ? kx : kx - N;
     const int fy = ky < N / 2 ? ky : ky - N;
     const uint32_t k2 = (uint32_t)(fx * fx) + (uint32_t)(fy * fy);
@@ -375,10 +378,11 @@ __device__ __forceinline__ cpx<float> spectrum_coeff<float>(int kx, int ky, int 
     // amp = amp0 k2^(-beta/4): log2 of the mantissa in FP32, the product with
     // -beta/4 in FP64, exp2 of the fractional part in FP32.
     int ex;
-    const float mant = frexpf((float)k2, &ex);
-    const double y = p.neg_beta_4 * ((double)ex + (double)log2f(mant));
+    const float mant = frexpf((float)k2, &ex);  // in [1/2, 1)
+    const double y = p.neg_beta_4 * ((double)ex + (double)__builtin_amdgcn_logf(mant));
     const double n = floor(y);
-    const float amp = ldexpf((float)p.amp0 * exp2f((float)(y - n)), (int)n) * 0.70710678118654752f;
+    const float amp =
+        ldexpf((float)p.amp0 * __builtin_amdgcn_exp2f((float)(y - n)), (int)n) * 0.70710678118654752f;
     return {amp * rad * cs, amp * rad * sn};
 }
 
