@@ -221,13 +221,40 @@ struct U32x4 {
     uint32_t x0, x1, x2, x3;
 };
 
+// a ^ b ^ k with the key k uniform over the wave (held in a scalar
+// register): one three-input logic instruction (truth table 0x96, the
+// three-way exclusive or), which the compiler does not form from the two
+// exclusive ors by itself
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+#ifndef SCINT_PHILOX_BITOP3
+#define SCINT_PHILOX_BITOP3 1
+#endif
+#if SCINT_PHILOX_BITOP3
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+#else
+    return a ^ b ^ k;
+#endif
+}
+
+// The keys k0, k1 must be the same for every lane of the wave (they are the
+// seed's two halves plus round constants at every call site).
 __device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         // each 32 x 32 -> 64-bit product as one full-width multiply (one
         // v_mad_u64_u32) rather than separate high and low halves
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x0, p1 = (uint64_t)0xCD9E8D57u * c.x2;
-        c = U32x4{(uint32_t)(p1 >> 32) ^ c.x1 ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.x3 ^ k1, (uint32_t)p0};
+        if (round < 2) {
+            // the first rounds still mix words that are uniform in some
+            // callers (a row's kx, the realisation), which the compiler folds
+            // into scalar instructions
+            c = U32x4{(uint32_t)(p1 >> 32) ^ c.x1 ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.x3 ^ k1, (uint32_t)p0};
+        } else {
+            c = U32x4{xor3_key((uint32_t)(p1 >> 32), c.x1, k0), (uint32_t)p1,
+                      xor3_key((uint32_t)(p0 >> 32), c.x3, k1), (uint32_t)p0};
+        }
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
