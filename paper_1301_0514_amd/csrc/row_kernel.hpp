@@ -359,15 +359,16 @@ template <>
 __device__ __forceinline__ cpx<float> spectrum_coeff<float>(int kx, int ky, int N, uint32_t r,
                                                             const RowProgram &p) {
     const U32x4 w = philox4x32_10(U32x4{(uint32_t)kx, (uint32_t)ky, r, 0u}, p.seed_lo, p.seed_hi);
-    const uint64_t a = ((uint64_t)w.x0 << 32) | w.x1;
-    const uint64_t b = ((uint64_t)w.x2 << 32) | w.x3;
-    const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53;
-    const double u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
+    // the uniforms ((x_hi 2^32 + x_lo) >> 11) + 1/2) 2^-53 of the FP64 path,
+    // formed in FP32 as (x_hi + x_lo 2^-32) 2^-32 + 2^-54: within an ulp of
+    // the FP64 value rounded to FP32, and never zero (the smallest is 2^-54)
+    const float u1 = fmaf((float)w.x1, 0x1.0p-64f, fmaf((float)w.x0, 0x1.0p-32f, 0x1.0p-54f));
+    const float u2 = fmaf((float)w.x3, 0x1.0p-64f, fmaf((float)w.x2, 0x1.0p-32f, 0x1.0p-54f));
     // hardware transcendentals, their arguments in range by construction:
     // -2 ln u1 = -2 ln 2 log2 u1 (u1 >= 2^-54, a normal float); the angle
     // 2 pi (u2 - rint(u2)) as the turns the hardware sine and cosine take
-    const float rad = sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf((float)u1));
-    const float turn = (float)(u2 - rint(u2));
+    const float rad = sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(u1));
+    const float turn = u2 - rintf(u2);
     const float sn = __builtin_amdgcn_sinf(turn), cs = __builtin_amdgcn_cosf(turn);
     const int fx = kx < N / 2 ? kx : kx - N;
     const int fy = ky < N / 2 ? ky : ky - N;
