@@ -594,8 +594,8 @@ def main(argv=None) -> int:
 
             tg = timed(lambda: fwd_adj(True), 3)
             tr = timed(lambda: fwd_adj(False), 3)
-            # survey model: forward 44 B/pt (screen, field and pattern kept) +
-            # adjoint 36 B/pt
+            # algorithmic bytes: forward 44 B/pt (screen, field and pattern
+            # kept) + adjoint 36 B/pt
             sec["grad_2048x16_forward_adjoint"] = {"ms_per_step": tg, "pt_per_s": nr * g.N ** 2 / (tg / 1e3),
                                                    "ms_per_step_recomputing_adjoint": tr,
                                                    "frac_of_hbm_roofline_80B_per_pt":
