@@ -176,7 +176,11 @@ int fresnel_propagate_field(int N, double delta, double lambda, double z, const 
  *              or NULL
  * The FP32 screen's lowest Fourier modes (|kx'|, |ky'| <= 16) are synthesised
  * in FP64 and the phase of exp(i phi) is formed from the screen to FP64
- * accuracy; phi_out holds the screen rounded once to FP32.
+ * accuracy; phi_out holds the screen rounded once to FP32.  With phi_out and
+ * field_out both NULL the screen is made transposed and the two propagation
+ * passes run in the other order (no final transpose): the same pattern up to
+ * the rounding of the differently ordered transforms, not bit for bit the
+ * one a call that also returns the screen gives.
  */
 int ps_screen_fresnel(int N, double delta, double r_diff, double beta, uint64_t seed,
                       uint32_t first_realisation, int n_real, double lambda, double z,
