@@ -567,9 +567,15 @@ __device__ __forceinline__ void exec_op(RowState<Real, L, V> &st, const RowOp &o
             for (int m = 0; m < E; ++m) v[m] = cmul(v[m], tab[m * T]);
         }
     } else if constexpr (CODE == ROP_MUL_RTAB2D) {
-        const Real *tab = static_cast<const Real *>(op.ptr) + off;
+        // element e = t + m T lies in the lower half for m < E/2 and mirrors
+        // to N - e = (E - m) T - t for m >= E/2 (E even)
+        static_assert(E % 2 == 0, "elements per thread must be even");
+        const int r = st.row <= L / 2 ? st.row : L - st.row;
+        const Real *tab = static_cast<const Real *>(op.ptr) + (int64_t)st.it * op.iter_stride +
+                          (int64_t)r * op.row_stride;
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = cscale(v[m], tab[m * T]);
+        for (int m = 0; m < E; ++m)
+            v[m] = cscale(v[m], m < E / 2 ? tab[st.t + m * T] : tab[(E - m) * T - st.t]);
     } else if constexpr (CODE == ROP_MUL_RLOAD) {
         const Real *src = static_cast<const Real *>(op.ptr) + off;
         const Real sc = (Real)op.param;

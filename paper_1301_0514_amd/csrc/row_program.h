@@ -26,7 +26,8 @@ enum RowOpCode : int32_t {
     ROP_FFT_FWD,     // v = DFT(v)   (kernel exp(-2 pi i e k / N))
     ROP_FFT_INV,     // v = IDFT(v)  (kernel exp(+2 pi i e k / N), unnormalised)
     ROP_MUL_TAB,     // v *= tab[e]  (complex table along the row; flag 1: conjugate)
-    ROP_MUL_RTAB2D,  // v *= tab[row][e]  (real 2-D table, no batch offset)
+    ROP_MUL_RTAB2D,  // v *= tab[min(row, N - row)][min(e, N - e)]: the quarter 0..N/2 x 0..N/2 of a real
+                     //   table even in both signed indices (row_stride N/2 + 1; no batch offset)
     ROP_MUL_RLOAD,   // v *= param * src[e]  (real array)
     ROP_SQRT2RE,     // v = (sqrt(2) Re v, 0); FP32: v = (hi, lo) of sqrt(2) Re v
                      //   plus the FP64 low modes of the row (low_tab)

@@ -1600,9 +1600,15 @@ int ps_plan_polychromatic(int N, int n_real, int n_lambda, int dtype, size_t bud
     return PS_OK;
 }
 
+// Elements of one disk spectrum as kept: the quarter [0, N/2] x [0, N/2] of
+// the N x N table (the disk, centred at the origin with minimum-image
+// offsets, is even in x and in y, so its spectrum is even in kx' and ky').
+static size_t disk_quarter_elems(int N) { return (size_t)(N / 2 + 1) * (N / 2 + 1); }
+
 // Spectra of the normalised disks of radii Rpx[j] pixels, divided by N^2 (the
-// inverse-transform normalisation), as n_r contiguous real N x N tables
-// indexed [kx][ky]; cached per (N, dtype, radii).
+// inverse-transform normalisation), as n_r contiguous real tables of the
+// quarter kx, ky in [0, N/2] of the spectrum indexed [kx][ky] (row length
+// N/2 + 1; ROP_MUL_RTAB2D mirrors the rest); cached per (N, dtype, radii).
 static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hipStream_t stream,
                             const void **out) {
     int dev;
@@ -1622,14 +1628,15 @@ static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hi
     if (int rc = refuse_in_capture(stream, "building the disk spectra of these radii")) return rc;
     const size_t rb = (size_t)nn(N) * real_bytes(dtype);
     const size_t cb = 2 * rb;
+    const size_t qb = disk_quarter_elems(N) * real_bytes(dtype);
     void *block = nullptr;
-    if (hipMalloc(&block, rb * Rpx.size()) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of disk spectra failed");
+    if (hipMalloc(&block, qb * Rpx.size()) != hipSuccess) return fail(PS_E_ALLOC, "hipMalloc of disk spectra failed");
     void *tmp = nullptr;
-    if (hipMalloc(&tmp, 2 * cb) != hipSuccess) {
+    if (hipMalloc(&tmp, 2 * cb + rb) != hipSuccess) {
         (void)hipFree(block);
         return fail(PS_E_ALLOC, "hipMalloc of disk workspace failed");
     }
-    char *W1 = static_cast<char *>(tmp), *W2 = W1 + cb;
+    char *W1 = static_cast<char *>(tmp), *W2 = W1 + cb, *tab = W2 + cb;  // tab: the full N x N table
     int rc = PS_OK;
     for (size_t j = 0; j < Rpx.size() && !rc; ++j) {
         // pixel count of the disk, same test as the disk image kernel
@@ -1643,7 +1650,6 @@ static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hi
                 if (dx * dx + dy * dy <= r2) count += 1.0;
             }
         }
-        char *tab = static_cast<char *>(block) + j * rb;
         hipError_t e = launch_disk_image(tab, N, r2, 1.0 / count, dtype == PS_F64, stream);
         if (e != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk image: ") + hipGetErrorString(e));
         if (!rc) {
@@ -1656,6 +1662,13 @@ static int get_disk_spectra(int N, const std::vector<double> &Rpx, int dtype, hi
             ProgBuilder b(N, N);
             b.op(ROP_LOAD_C, W2, 0, N).op(ROP_FFT_FWD).op(ROP_STORE_R, tab, 0, N, 0, 0, 1.0 / (double)nn(N));
             rc = run_row<ProgFwdReTag>(dtype, N, b.p, b.n, stream);
+        }
+        if (!rc) {
+            // keep the quarter: rows kx <= N/2, their first N/2 + 1 entries
+            const size_t w = (size_t)(N / 2 + 1) * real_bytes(dtype);
+            hipError_t e2 = hipMemcpy2DAsync(static_cast<char *>(block) + j * qb, w, tab, (size_t)N * real_bytes(dtype), w,
+                                             (size_t)(N / 2 + 1), hipMemcpyDeviceToDevice, stream);
+            if (e2 != hipSuccess) rc = fail(PS_E_DEVICE, std::string("disk spectrum copy: ") + hipGetErrorString(e2));
         }
     }
     if (!rc) {
@@ -1711,7 +1724,7 @@ static ProgBuilder smear_mid_prog(int N, const SmearJob &j, const void *D, int n
         .op(ROP_SAVE)
         .op(ROP_LOOP)
         .op(ROP_RESTORE)
-        .op(ROP_MUL_RTAB2D, D, 0, N, nn(N))
+        .op(ROP_MUL_RTAB2D, D, 0, N / 2 + 1, disk_quarter_elems(N))
         .op(ROP_FFT_INV)
         .op(ROP_STORE_C, j.V1, (int64_t)n_r * nn(N), N, nn(N))
         .op(ROP_ENDLOOP);
