@@ -110,17 +110,49 @@ template <int R, int S> struct RootTable {
 
 // ---------------------------------------------------------------------------
 // In-register DFT of size R:  a[k] <- sum_n a[n] exp(S 2 pi i n k / R).
-// Base radices 2, 4, 5; larger radices by one Cooley-Tukey split R = R1 R2
-// (decimation in time) with compile-time twiddles.
+// Base radices 2, 4, 5.  An even R >= 8 is split R = (R/2) x 2 by decimation
+// in time: two half-size DFTs of the even and odd elements, then R/2 radix-2
+// butterflies whose compile-time twiddle multiplies one input, which a
+// butterfly takes in six fused multiply-adds (below) instead of a complex
+// product and four additions.
 // ---------------------------------------------------------------------------
-#ifndef SCINT_SPLIT32
-#define SCINT_SPLIT32 4
+#ifndef SCINT_DFT_DIT2
+#define SCINT_DFT_DIT2 1
 #endif
 template <int R> constexpr int split_factor() {
-    if constexpr (R == 32) return SCINT_SPLIT32;
+    if constexpr (SCINT_DFT_DIT2 && R % 2 == 0 && R >= 8) return R / 2;
+    else if constexpr (R == 32) return 4;
     else if constexpr (R % 4 == 0 && R != 8) return 4;
     else if constexpr (R % 2 == 0) return 2;
     else return 5;
+}
+
+template <typename Real> __device__ __forceinline__ Real fmar(Real a, Real b, Real c) {
+    if constexpr (sizeof(Real) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// (a, b) <- (a + w b, a - w b) for a constant w = c + i s (Linzer & Feig):
+// w b = c (b + i (s/c) b) when |c| >= |s|, else s ((c/s) b + i b), so that
+// the scaled product takes two fused multiply-adds and each output two more,
+// with the ratio at most 1 in magnitude.
+template <typename Real> __device__ __forceinline__ void bfly_const(cpx<Real> &a, cpx<Real> &b, double c, double s) {
+    Real vr, vi, g;
+    if (c * c >= s * s) {
+        const Real t = (Real)(s / c);
+        g = (Real)c;
+        vr = fmar(-t, b.im, b.re);
+        vi = fmar(t, b.re, b.im);
+    } else {
+        const Real u = (Real)(c / s);
+        g = (Real)s;
+        vr = fmar(u, b.re, -b.im);
+        vi = fmar(u, b.im, b.re);
+    }
+    const cpx<Real> x0 = {fmar(g, vr, a.re), fmar(g, vi, a.im)};
+    const cpx<Real> x1 = {fmar(-g, vr, a.re), fmar(-g, vi, a.im)};
+    a = x0;
+    b = x1;
 }
 
 template <int R, int S, typename Real> struct Dft;
@@ -175,6 +207,33 @@ template <int R, int S, typename Real> struct Dft {
     static constexpr int R2 = R / R1;
     static __device__ __forceinline__ void run(cpx<Real>* a) {
         constexpr RootTable<R, S> W{};
+        if constexpr (R2 == 2) {
+            // decimation in time: X[k] = E[k] + W^k O[k], X[k + R/2] = E[k] - W^k O[k]
+            cpx<Real> e[R1], o[R1];
+#pragma unroll
+            for (int n = 0; n < R1; ++n) {
+                e[n] = a[2 * n];
+                o[n] = a[2 * n + 1];
+            }
+            Dft<R1, S, Real>::run(e);
+            Dft<R1, S, Real>::run(o);
+#pragma unroll
+            for (int k = 0; k < R1; ++k) {
+                if (k == 0) {
+                    a[k] = cadd(e[k], o[k]);
+                    a[k + R1] = csub(e[k], o[k]);
+                } else if (4 * k == R) {
+                    const cpx<Real> t = mul_si<S>(o[k]);
+                    a[k] = cadd(e[k], t);
+                    a[k + R1] = csub(e[k], t);
+                } else {
+                    bfly_const(e[k], o[k], W.c[k], W.s[k]);
+                    a[k] = e[k];
+                    a[k + R1] = o[k];
+                }
+            }
+            return;
+        }
         cpx<Real> y[R];
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) {
