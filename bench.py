@@ -269,6 +269,23 @@ def main(argv=None) -> int:
     value = units / (ms_step / 1e3)
     log("timed %d steps (%s): %.2f ms/step (wall %.2f s)" % (args.steps, "graph replay" if graph else "eager",
                                                           ms_step, wall))
+    # the same step timed replay by replay (events around each), reported
+    # as the median beside the bracketed mean above
+    n_rep = max(20, args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_rep + 1)]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        evs[0].record()
+        for i in range(n_rep):
+            if graph is not None:
+                graph.replay()
+            else:
+                step()
+            evs[i + 1].record()
+    torch.cuda.synchronize()
+    per_rep = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(n_rep))
+    replays = {"n": n_rep, "median_ms": float(np.median(per_rep)), "min_ms": per_rep[0], "max_ms": per_rep[-1]}
+    log("%d single replays: median %.2f ms (%.2f-%.2f)" % (n_rep, replays["median_ms"], per_rep[0], per_rep[-1]))
     # per-kernel durations: the same step run eagerly with the library's
     # event timing on (events cannot be recorded per kernel inside a replay)
     scint.timing_enable(True)
@@ -356,6 +373,7 @@ def main(argv=None) -> int:
                    "workspace_budget_GiB": workspace_gib, "parallelism": "single GPU"},
         "roofline": roofline,
         "timing": "graph replay of the whole step" if graph is not None else "eager calls",
+        "replays": replays,
         "kernel_ms_per_step_eager": ms_eager,
         "step_algorithmic_GB": step_alg / 1e9,
         "step_algorithmic_bytes_per_pt_lambda": STEP_BYTES_PER_PT_LAMBDA,
