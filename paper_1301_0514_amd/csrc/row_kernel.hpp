@@ -438,8 +438,12 @@ template <typename Real, int L, int V> struct RowState {
 // x = t + m T with T/N = 1/E, so exp(2 pi i k x / N) = W^k c_m^k with
 // W = exp(2 pi i t / N) and c_m^k = exp(2 pi i m k / E) a compile-time
 // constant: the thread forms D[k] = G_y[k] W^k once, and element m is
-// sum_k Re D[k] cos(2 pi m k / E) - Im D[k] sin(2 pi m k / E), the two sums
-// shared with element E - m (same cosines, opposite sines).  The result is
+// P - Q with P = sum_k Re D[k] cos(2 pi m k / E), Q = sum_k Im D[k]
+// sin(2 pi m k / E); element E - m is P + Q (same cosines, opposite sines).
+// Each sum is split over even and odd k: at E/2 - m the cosines and sines
+// take the factors (-1)^k and -(-1)^k, so the same four partial sums give
+// elements E/2 - m and E/2 + m too, and a thread sums for m <= E/4 only.
+// The result is
 // kept as the pair v = (hi, lo), hi = phi rounded to FP32 and lo the FP32
 // remainder, so that the stored screen is phi correctly rounded and the phase
 // factor can take phi to FP64 accuracy (RF_HILO).
@@ -467,12 +471,24 @@ __device__ __forceinline__ void add_low_modes(cpx<float> *v, const void *low_tab
     }
     constexpr RootTable<E, 1> C{};  // cos, sin of 2 pi e / E
     constexpr double kSqrt2 = 1.41421356237309504880;
+    // phi at element j from the sums of its P and Q: P - Q, and P + Q at E - j
+    auto put = [&](int j, double P, double Q) {
+        const double phi = fma(kSqrt2, (double)v[j].re, P - Q);
+        const float hi = (float)phi;
+        v[j] = {hi, (float)(phi - (double)hi)};
+        if (j != 0 && j != E / 2) {
+            const double phi2 = fma(kSqrt2, (double)v[E - j].re, P + Q);
+            const float hi2 = (float)phi2;
+            v[E - j] = {hi2, (float)(phi2 - (double)hi2)};
+        }
+    };
 #pragma unroll
-    for (int m = 0; m <= E / 2; ++m) {
-        double P = 0.0, Q = 0.0;  // sum Re D cos, sum Im D sin
+    for (int m = 0; m <= E / 4; ++m) {
+        double Pk[2] = {0.0, 0.0}, Qk[2] = {0.0, 0.0};  // over even and odd k
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
             // exact 0 and +-1 factors as adds (IEEE forbids folding x * 0)
+            double &P = Pk[k & 1], &Q = Qk[k & 1];
             const int e = (m * k) % E;
             if (e == 0) {
                 P += dr[k];
@@ -487,14 +503,8 @@ __device__ __forceinline__ void add_low_modes(cpx<float> *v, const void *low_tab
                 Q = fma(di[k], C.s[e], Q);
             }
         }
-        const double phi = fma(kSqrt2, (double)v[m].re, P - Q);
-        const float hi = (float)phi;
-        v[m] = {hi, (float)(phi - (double)hi)};
-        if (m != 0 && m != E / 2) {
-            const double phi2 = fma(kSqrt2, (double)v[E - m].re, P + Q);
-            const float hi2 = (float)phi2;
-            v[E - m] = {hi2, (float)(phi2 - (double)hi2)};
-        }
+        put(m, Pk[0] + Pk[1], Qk[0] + Qk[1]);
+        if (E / 2 - m != m) put(E / 2 - m, Pk[0] - Pk[1], Qk[1] - Qk[0]);
     }
 }
 
